@@ -1,0 +1,12 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package holds configurations and input generators only; it performs no
+step of the reconstruction method.
+"""
+from .configs import (Config, CONFIGS, cfg_tiny, cfg_paper, cfg_precision, cfg_cnn, cfg_stream,
+                      with_frames, with_angles, with_blocks)
+from .medium import Medium, make_medium, point_medium
+
+__all__ = ["Config", "CONFIGS", "cfg_tiny", "cfg_paper", "cfg_precision", "cfg_cnn",
+           "cfg_stream", "with_frames", "with_angles", "with_blocks", "Medium", "make_medium",
+           "point_medium"]

@@ -1,0 +1,66 @@
+"""Seeded synthetic arrays used as stage inputs by tests and the benchmark.
+
+Every function returns plain numpy arrays drawn from numpy PCG64 with the given
+seed.  None of them performs any step of the method.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def complex_normal(shape, seed: int, scale: float = 1.0, dtype=np.complex64) -> np.ndarray:
+    """i.i.d. complex Gaussian with E|x|^2 = scale^2."""
+    g = rng(seed)
+    re = g.standard_normal(shape, dtype=np.float32 if dtype == np.complex64 else np.float64)
+    im = g.standard_normal(shape, dtype=np.float32 if dtype == np.complex64 else np.float64)
+    out = np.empty(shape, dtype=dtype)
+    out.real = re * (scale / np.sqrt(2.0))
+    out.imag = im * (scale / np.sqrt(2.0))
+    return out
+
+
+def clutter_stack(n_pix: int, n_frames: int, rank: int, seed: int, clutter_db: float = 40.0,
+                  decay: float = 0.7) -> np.ndarray:
+    """Casorati-shaped stack [F][n_pix] (complex64): a low-rank 'tissue' part with
+    decaying mode energies, plus a weak i.i.d. 'blood' part of unit rms."""
+    g = rng(seed)
+    frames = np.arange(n_frames)
+    out = np.zeros((n_frames, n_pix), dtype=np.complex128)
+    amp = 10.0 ** (clutter_db / 20.0)
+    for r in range(rank):
+        spatial = (g.standard_normal(n_pix) + 1j * g.standard_normal(n_pix)) / np.sqrt(2)
+        freq = g.uniform(-0.02, 0.02)
+        temporal = np.exp(2j * np.pi * freq * frames) * (1.0 + 0.3 * g.standard_normal(n_frames))
+        out += amp * (decay ** r) * temporal[:, None] * spatial[None, :]
+    out += (g.standard_normal((n_frames, n_pix)) + 1j * g.standard_normal((n_frames, n_pix))) \
+        / np.sqrt(2)
+    return out.astype(np.complex64)
+
+
+def gaussian_spots(nz: int, nu: int, n_spots: int, sigma: float, seed: int, spacing: float,
+                   margin: int = 8):
+    """A noise-free image made of isolated sampled 2D Gaussians.
+
+    Returns (image [nz][nu] float64, centres [n][2] as (z, u) in pixel units).
+    Centres are at least `spacing` pixels apart and `margin` pixels inside the
+    border; sub-pixel offsets are uniform in [-0.5, 0.5).
+    """
+    g = rng(seed)
+    centres = []
+    tries = 0
+    while len(centres) < n_spots and tries < 100000:
+        tries += 1
+        c = np.array([g.integers(margin, nz - margin), g.integers(margin, nu - margin)], float)
+        c += g.uniform(-0.5, 0.5, size=2)
+        if all(np.hypot(*(c - d)) >= spacing for d in centres):
+            centres.append(c)
+    centres = np.array(centres)
+    zz, uu = np.meshgrid(np.arange(nz), np.arange(nu), indexing="ij")
+    img = np.zeros((nz, nu))
+    for cz, cu in centres:
+        img += np.exp(-((zz - cz) ** 2 + (uu - cu) ** 2) / (2 * sigma ** 2))
+    return img, centres

@@ -1,0 +1,272 @@
+#!/usr/bin/env python
+"""Benchmark: milliseconds per 300-frame RCA ensemble on one MI355X.
+
+One step = the whole path on one ensemble whose IQ channel data (5.66 GB,
+300 frames x 2 orientations x 9 angles x 128 elements x 1024 samples, complex64)
+is already resident in HBM: stage-1 DAS -> stage-2 projection -> clutter filter
+(FP64-accumulated Gram, FP64 eigen, FP64 removal; or the BF16 split form) ->
+NCC localisation.  The IQ comes from the library's forward simulator of a
+synthetic medium shaped like the paper's pig-kidney acquisition (2000 MBs on
+vessel splines, 20000 tissue scatterers 40 dB above the MBs, rigid 0.2 mm
+1 Hz motion), generated on the GPU before timing.
+
+Prints one JSON line.  `roofline` is for the dominant kernel (stage-1 DAS,
+VALU-bound); `cpu_baseline` times the FP64 oracle on a bounded sample on the
+host cores (rank 0, N=1 only).
+
+Sub-commands used to produce the committed profiles:
+  --profile-das       run the simulator, one stage-1 launch and a 1 GiB copy
+                      (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs)
+  --summarize-pmc DIR write the counter summary from two rocprofv3 --pmc runs
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+DAS_FLOPS_PER_EVAL = 14        # complex lerp (2 sub + 2 FMA = 6) + complex multiply-add (8)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "das_stage1_paper_counters.json")
+DAS_SOURCE = os.path.join(ROOT, "paper_2511_21647_amd", "csrc", "beamform.hip")
+COPY_BYTES = 1 << 30
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    return hashlib.sha256(open(DAS_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def setup(precision: str, ensemble: int = 0):
+    import numpy as np
+    import torch
+    import paper_2511_21647_amd as ulm
+    from synth import cfg_paper, make_medium
+
+    cfg = cfg_paper()
+    prec = ulm.ULM_PREC_BF16X3 if precision == "bf16x3" else ulm.ULM_PREC_FP64GRAM
+    t0 = time.time()
+    med = make_medium(cfg, ensemble)
+    ctx = ulm.Context(cfg, precision=prec)
+    pos = torch.from_numpy(np.ascontiguousarray(med.pos)).cuda()
+    amp = torch.from_numpy(med.amp).cuda()
+    iq = ulm.ulm_sim_channel_data(ctx, pos, amp, med.noise_seed, med.noise_sigma)
+    torch.cuda.synchronize()
+    del pos, amp
+    log(f"setup: medium + GPU simulation of {tuple(iq.shape)} IQ in {time.time() - t0:.1f} s")
+    return cfg, ctx, iq
+
+
+def das_evals(cfg) -> int:
+    g = cfg.grid
+    return 2 * cfg.n_angles * cfg.seq.n_frames * g.nz * g.nu * cfg.probe.n_elem
+
+
+def run_gpu(args):
+    import torch
+    import paper_2511_21647_amd as ulm
+
+    cfg, ctx, iq = setup(args.precision)
+    cap = 4_000_000
+    proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device="cuda")
+    eig = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device="cuda")
+    locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        ulm.rca_beamform_stage1(ctx, iq)
+        if ev: ev[1].record()
+        ulm.rca_beamform_stage2(ctx, proj)
+        if ev: ev[2].record()
+        ulm.svd_clutter_filter(ctx, proj, eig)
+        if ev: ev[3].record()
+        ulm.ncc_localize(ctx, proj, cap, locs, count)
+        if ev: ev[4].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ulm.ulm_check_status(ctx, count, cap)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ulm.ulm_check_status(ctx, count, cap)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    names = ["das_stage1", "stage2_projection", "clutter_filter", "ncc_localize"]
+    stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps
+             for i, n in enumerate(names)}
+    n_det = int(count.item())
+    return cfg, ms_step, stage, n_det
+
+
+def roofline(cfg, das_ms):
+    flops = DAS_FLOPS_PER_EVAL * das_evals(cfg)
+    achieved = flops / (das_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(COUNTERS_FILE):
+        rec = json.load(open(COUNTERS_FILE))
+        if rec.get("source_sha") == source_hash():
+            traffic = rec["hbm_bytes_per_launch"]
+    return {"bound": "alu", "kernel": "das_stage1_kernel", "achieved": round(achieved, 2),
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+            "algorithmic_flops": flops, "launch_ms": round(das_ms, 3)}
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to one
+    ensemble: stage 1 + stage 2 for two frames, the clutter filter of one full
+    plane (68,500 px x 300 frames), NCC localisation of one frame of one plane."""
+    import numpy as np
+    from synth import arrays, with_frames
+    from oracle import beamform, clutter, localize
+
+    F = cfg.seq.n_frames
+    nf = 2
+    one = with_frames(cfg, nf)
+    iq = arrays.complex_normal(one.iq_shape, seed=77, dtype=np.complex128)
+    t = time.perf_counter()
+    S = beamform.stage1_slices(iq, one)
+    t_s1 = time.perf_counter() - t
+    t = time.perf_counter()
+    P = beamform.stage2_project(S, one)
+    t_s2 = time.perf_counter() - t
+    stack = arrays.clutter_stack(cfg.grid.nz * cfg.grid.nu, F, rank=20, seed=78)
+    t = time.perf_counter()
+    clutter.clutter_filter(stack.astype(np.complex128), cfg.svd_cutoff)
+    t_f = time.perf_counter() - t
+    t = time.perf_counter()
+    localize.localize(P[:1, :1, :1], cfg)
+    t_n = time.perf_counter() - t
+    total_s = (t_s1 + t_s2) * F / nf + t_f * 2 + t_n * 2 * F
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    return {"value": round(total_s * 1e3, 1), "unit": "ms/ensemble",
+            "cores": min(threads, os.cpu_count()), "kind": "oracle",
+            "sample": (f"stage-1 DAS + stage-2 projection of {nf} of {F} frames "
+                       f"({t_s1:.2f} + {t_s2:.2f} s), clutter filter of 1 of 2 full planes "
+                       f"({t_f:.2f} s), NCC localisation of 1 of {2 * F} images ({t_n:.2f} s); "
+                       f"scaled to a whole ensemble")}
+
+
+def profile_das(args):
+    import torch
+    import paper_2511_21647_amd as ulm
+    cfg, ctx, iq = setup("fp64gram")
+    ulm.rca_beamform_stage1(ctx, iq)
+    torch.cuda.synchronize()
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile run done: one das_stage1_kernel launch and one 1 GiB copy")
+
+
+def _read_counter_rows(d):
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_pmc(d_fetch, d_write):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the DAS kernel, scaled by the
+    counter reading of a plain 1 GiB copy (a copy reads and writes COPY_BYTES)."""
+    def per_kernel(d, counter):
+        out = {}
+        for r in _read_counter_rows(d):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r.get("Kernel_Name", "")
+            out.setdefault(name, 0.0)
+            out[name] += float(r["Counter_Value"])
+        return out
+
+    fetch = per_kernel(d_fetch, "FETCH_SIZE")
+    write = per_kernel(d_write, "WRITE_SIZE")
+    das = [k for k in fetch if "das_stage1" in k]
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    if not das or not copy:
+        raise SystemExit(f"kernels not found: {list(fetch)[:8]}")
+    f_das, w_das = fetch[das[0]], write.get(das[0], 0.0)
+    f_cp, w_cp = fetch[copy[0]], write.get(copy[0], 0.0)
+    f_scale = COPY_BYTES / (f_cp * 1024.0)
+    w_scale = COPY_BYTES / (w_cp * 1024.0) if w_cp > 0 else 1.0
+    rec = {"kernel": das[0], "copy_kernel": copy[0], "fetch_kib": f_das, "write_kib": w_das,
+           "copy_fetch_kib": f_cp, "copy_write_kib": w_cp, "fetch_scale": f_scale,
+           "write_scale": w_scale,
+           "hbm_bytes_per_launch": f_das * 1024.0 * f_scale + w_das * 1024.0 * w_scale,
+           "source_sha": source_hash()}
+    os.makedirs(os.path.dirname(COUNTERS_FILE), exist_ok=True)
+    with open(COUNTERS_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64gram", "bf16x3"], default="fp64gram")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-das", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not supported "
+                                   "(ensembles shard across GPUs with no communication)"}))
+        sys.exit(2)
+    if args.profile_das:
+        profile_das(args)
+        return
+    cfg, ms_step, stage, n_det = run_gpu(args)
+    g = cfg.grid
+    out = {
+        "metric": "ms per 300-frame RCA ensemble (plain FP32 vs BF16+CNN), HBM/MFMA roofline %",
+        "value": round(ms_step, 3), "unit": "ms/ensemble", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp64gram" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale RCA ensemble: 128+128 elements, 9 angles/orientation, "
+                               "300 frames, 1024 samples, two 250x274 planes, SVD cutoff 20, "
+                               "9x9 NCC",
+                   "precision": args.precision, "frames": cfg.seq.n_frames,
+                   "planes": [2 * g.n_blocks, g.nz, g.nu]},
+        "stages_ms": {k: round(v, 3) for k, v in stage.items()},
+        "ensembles_per_s": round(1e3 / ms_step, 2),
+        "realtime_ratio_vs_750ms": round(ms_step / 750.0, 4),
+        "detections": n_det,
+        "roofline": roofline(cfg, stage["das_stage1"]),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on host cores) ...")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

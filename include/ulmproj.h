@@ -1,0 +1,223 @@
+/*
+ * ulmproj: projection-based RCA ULM reconstruction on AMD MI355X (gfx950).
+ *
+ * C ABI of libulmproj.so.  Plain C types only: buffers are raw pointers,
+ * sizes are integers, the stream is an opaque hipStream_t passed as void*.
+ *
+ * Conventions for every entry point
+ *   - SI units (m, s, Hz, rad).  Complex values are interleaved float pairs
+ *     (re, im) ("c64") or double pairs ("c128"); arrays are row-major with the
+ *     last index fastest.
+ *   - Device buffers are owned by the caller (allocated on the device that was
+ *     current at ulm_create).  The context owns only its small tables.
+ *   - The workspace `ws` (ws_bytes >= ulm_workspace_size) is caller-owned
+ *     device memory; its contents between calls are unspecified, except that
+ *     ulm_check_status reads the status word the last call left there.
+ *   - Calls are asynchronous on `stream` (NULL = the default stream); results
+ *     are valid once the caller synchronises that stream.  No entry point
+ *     allocates memory, and none synchronises the stream except
+ *     ulm_check_status.
+ *   - Every entry point returns ULM_OK (0) or a negative error code;
+ *     ulm_last_error() returns a thread-local message for the last error.
+ *   - Two calls that share a workspace must not overlap in time.
+ *
+ * The method (paper: "Fast 3D Ultrasound Localization Microscopy via
+ * Projection-based Processing Framework"):
+ *   Section II-A1  two-stage beamforming: stage-1 reference slice per transmit,
+ *                  stage-2 extrapolation along the transmit direction with a
+ *                  rigid axial shift, coherent compounding;
+ *   Section II-A4  sub-block sum projection onto x-z / y-z planes;
+ *   Section II-A2  eigen-based SVD clutter filter: covariance of the Casorati
+ *                  matrix, eigendecomposition, projection removal;
+ *   Section II-A4  NCC with a Gaussian PSF (separable 1D correlations, Fig. 1g),
+ *                  maximum-intensity threshold, sub-pixel regional peaks.
+ */
+#ifndef ULMPROJ_H
+#define ULMPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ULM_OK                   0
+#define ULM_ERR_INVALID_ARG     -1   /* bad pointer, size or configuration        */
+#define ULM_ERR_HIP             -2   /* a HIP runtime call failed                 */
+#define ULM_ERR_OVERFLOW        -3   /* more localisations than `capacity`        */
+#define ULM_ERR_NUMERIC         -4   /* non-finite input to the clutter filter    */
+#define ULM_ERR_NOT_IMPLEMENTED -5
+
+#define ULM_MAX_ANGLES 32
+
+/* precision of the Casorati Gram and the clutter removal */
+#define ULM_PREC_FP64GRAM 0   /* plain path: FP32 data, Gram and removal accumulated in FP64 */
+#define ULM_PREC_BF16X3   1   /* BF16 hi/lo split products on MFMA, FP32 accumulation       */
+
+typedef struct ulm_config {
+    /* probe: n_elem row elements and n_elem column elements */
+    int32_t n_elem;
+    int32_t n_samp;       /* IQ samples per channel                          */
+    int32_t n_frames;     /* frames (volumes) per ensemble                   */
+    int32_t n_angles;     /* plane-wave angles per orientation (<= 32)       */
+    double  pitch;        /* element pitch, m                                */
+    double  c;            /* speed of sound, m/s                             */
+    double  f0;           /* centre frequency, Hz                            */
+    double  fs;           /* IQ sampling rate, Hz                            */
+    double  t_start;      /* time of IQ sample 0 after the firing, s         */
+    double  bandwidth;    /* fractional -6 dB bandwidth (simulator pulse)    */
+    double  angles_rad[ULM_MAX_ANGLES];
+    /* projection-plane grid; pixel centres u0 + i*du, z0 + l*dz, v0 + m*dv */
+    int32_t nu, nz, nv, n_blocks;
+    double  du, dz, u0, z0, dv, v0;
+    double  v_ref;        /* stage-1 reference slice position on v           */
+    /* clutter filter and localisation */
+    int32_t svd_cutoff;   /* number of removed modes, 0 <= c <= n_frames     */
+    int32_t ncc_size;     /* odd template size, 3..15                        */
+    int32_t precision;    /* ULM_PREC_*                                      */
+    int32_t reserved;
+    double  sigma_u, sigma_z;   /* template sigmas, pixels                   */
+    double  tau_ncc;            /* NCC threshold                             */
+    double  alpha;              /* intensity threshold / frame maximum       */
+} ulm_config_t;
+
+/* One localisation.  plane = orientation * n_blocks + block; positions are in
+ * pixel units of the plane grid (pixel centres at integers). */
+typedef struct ulm_loc {
+    int32_t plane;
+    int32_t frame;
+    int32_t iz, iu;       /* integer peak pixel                              */
+    float   z, u;         /* sub-pixel position                              */
+    float   ncc;          /* NCC at the peak                                 */
+    float   intensity;    /* envelope at the peak                            */
+} ulm_loc_t;
+
+typedef struct ulm_timing {
+    float ms_beamform, ms_filter, ms_localize, ms_total;
+} ulm_timing_t;
+
+typedef struct ulm_ctx ulm_ctx_t;
+
+/* Thread-local message for the last error returned on this thread. */
+const char *ulm_last_error(void);
+
+/*
+ * Validate `cfg`, build the per-geometry tables (stage-2 axial taps, per-depth
+ * transmit delays and phases, NCC template taps) on the current device and
+ * return a context.  Errors: INVALID_ARG (bad configuration, including a
+ * geometry whose delay span does not fit the beamformer's sample window), HIP.
+ */
+int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out);
+int32_t ulm_destroy(ulm_ctx_t *ctx);
+
+/* Bytes of device workspace every call below needs. */
+int32_t ulm_workspace_size(const ulm_ctx_t *ctx, size_t *bytes);
+
+/*
+ * Two-stage beamforming straight to projection planes (Section II-A1 and the
+ * sub-block projection of Section II-A4).
+ *   iq   [F][2][K][Nc][Ns] c64, device: IQ channel data; orientation 0 = RC
+ *        (transmit rows, receive columns: x-z plane), 1 = CR (y-z plane).
+ *   proj [2][B][F][Nz][Nu] c64, device, written:
+ *        P_{o,b}(u,z) = sum_k sum_{m in block b} S_k^lin(u, z + (v_m - v_ref) t_k)
+ *                       * exp(i 4 pi f0 (v_m - v_ref) t_k / c),  t_k = tan(theta_k / 2),
+ *        S_k(u,z) = sum_e IQ^lin_{k,e}((tau - t_start) fs) exp(i 2 pi f0 (tau - 2z/c)),
+ *        tau = tau_tx(v_ref, z; theta_k) + tau_rx(u, z; e).
+ * Errors: INVALID_ARG (NULL pointer, ws too small), HIP.
+ */
+int32_t rca_beamform_proj(ulm_ctx_t *ctx, const float *iq, float *proj, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/*
+ * The two halves of rca_beamform_proj, for callers that time or overlap them.
+ * rca_beamform_stage1 writes the stage-1 reference slices
+ *   S[o][k][f][z][u] (c64) into the workspace;
+ * rca_beamform_stage2 reads them from the same workspace and writes `proj`
+ * (stage-2 extrapolation, compounding and slab projection as an axial FIR).
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t rca_beamform_stage1(ulm_ctx_t *ctx, const float *iq, void *ws, size_t ws_bytes,
+                            void *stream);
+int32_t rca_beamform_stage2(ulm_ctx_t *ctx, float *proj, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Eigen-based SVD clutter filter of every plane (Section II-A2), in place.
+ *   proj    [2][B][F][Nz*Nu] c64, device, in/out.  Each plane's Casorati matrix
+ *           I (pixels x frames) becomes I - (I V_c) V_c^H, V_c the eigenvectors of
+ *           the svd_cutoff largest eigenvalues of C = I^H I (FP64 eigensolver).
+ *   eigvals [2][B][F] f64, device, may be NULL: eigenvalues of C, descending.
+ * A plane with a non-finite covariance is left unfiltered and flags the status
+ * word (see ulm_check_status).  Errors: INVALID_ARG, HIP.
+ */
+int32_t svd_clutter_filter(ulm_ctx_t *ctx, float *proj, double *eigvals, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/*
+ * NCC localisation (Section II-A4) on filtered planes.
+ *   filtered [2][B][F][Nz][Nu] c64, device.
+ *   locs     [capacity] ulm_loc_t, device: the first min(total, capacity)
+ *            detections sorted by (plane, frame, iz, iu).
+ *   count    int32, device: total number of detections (may exceed capacity;
+ *            ulm_check_status then returns ULM_ERR_OVERFLOW).
+ * Detection: NCC >= tau_ncc, envelope >= alpha * frame maximum, NCC above the
+ * 3x3 neighbours earlier in raster order and not below the later ones;
+ * sub-pixel offsets by a 3-point Gaussian fit per axis (parabolic when a value
+ * is <= 0), clamped to +-0.5.  Errors: INVALID_ARG, HIP.
+ */
+int32_t ncc_localize(ulm_ctx_t *ctx, const float *filtered, ulm_loc_t *locs, int32_t capacity,
+                     int32_t *count, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The whole path on one ensemble: rca_beamform_proj -> svd_clutter_filter ->
+ * ncc_localize.  `proj` receives the filtered planes.  `timing` (host, may be
+ * NULL) receives per-stage milliseconds; a non-NULL `timing` synchronises the
+ * stream at the end of the call.
+ */
+int32_t ulm_reconstruct_ensemble(ulm_ctx_t *ctx, const float *iq, float *proj,
+                                 double *eigvals, ulm_loc_t *locs, int32_t capacity,
+                                 int32_t *count, void *ws, size_t ws_bytes,
+                                 ulm_timing_t *timing, void *stream);
+
+/*
+ * Synchronise `stream`, then report the status the last svd_clutter_filter /
+ * ncc_localize call left in `ws`: ULM_OK, ULM_ERR_NUMERIC (a plane was not
+ * filtered) or ULM_ERR_OVERFLOW (count > capacity).  `capacity` is the value
+ * passed to the last ncc_localize (or -1 to skip that check); `count` is that
+ * call's device counter (may be NULL).
+ */
+int32_t ulm_check_status(ulm_ctx_t *ctx, void *ws, const int32_t *count, int32_t capacity,
+                         void *stream);
+
+/*
+ * Forward model of the channel data (input generator; not part of the timed
+ * path).  For every frame f, orientation o, angle k, element e and sample s:
+ *   IQ = sum_q amp_q exp(-(t_s - tau_q)^2 / (2 sigma_t^2)) exp(-i 2 pi f0 tau_q) + n
+ *   sigma_t = sqrt(2 ln 2) / (pi bandwidth f0); the Gaussian is truncated where
+ *   it falls below 1e-9; n = Philox4x32-10 / Box-Muller complex noise of rms
+ *   noise_sigma keyed by noise_seed and the sample's flat index.
+ *   pos [F][S][3] f64, device: scatterer (x, y, z) per frame.
+ *   amp [S] c128, device.   iq [F][2][K][Nc][Ns] c64, device, written.
+ * Scatterers are accumulated with LDS float atomics: results agree with an
+ * exact sum to ~1e-7 but are not bitwise reproducible.
+ */
+int32_t ulm_sim_channel_data(ulm_ctx_t *ctx, const double *pos, const double *amp,
+                             int32_t n_scat, uint64_t noise_seed, double noise_sigma,
+                             float *iq, void *stream);
+
+/*
+ * Accumulate localisations into per-plane density maps on a grid `upsample`
+ * times finer than the planes (pixel i covers [i - 0.5, i + 0.5); fine bin
+ * floor((x + 0.5) * upsample)); out-of-grid records are skipped.
+ *   locs [n] ulm_loc_t device (n read from the device `count`, clipped to
+ *   capacity); density [2*B][Nz*up][Nu*up] uint32, device, incremented.
+ */
+int32_t ulm_density_accumulate(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
+                               int32_t capacity, int32_t upsample, uint32_t *density,
+                               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ULMPROJ_H */

@@ -1,0 +1,319 @@
+"""ctypes binding of libulmproj.so.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  There is no
+fallback: if the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libulmproj.so")
+
+ULM_OK = 0
+ULM_ERR_INVALID_ARG = -1
+ULM_ERR_HIP = -2
+ULM_ERR_OVERFLOW = -3
+ULM_ERR_NUMERIC = -4
+ULM_ERR_NOT_IMPLEMENTED = -5
+ULM_MAX_ANGLES = 32
+ULM_PREC_FP64GRAM = 0
+ULM_PREC_BF16X3 = 1
+
+EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
+           "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
+           "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate")
+
+
+class ULMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ulmproj error {code}: {msg}")
+        self.code = code
+
+
+class ULMConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_elem", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+        ("n_angles", ctypes.c_int32),
+        ("pitch", ctypes.c_double), ("c", ctypes.c_double), ("f0", ctypes.c_double),
+        ("fs", ctypes.c_double), ("t_start", ctypes.c_double), ("bandwidth", ctypes.c_double),
+        ("angles_rad", ctypes.c_double * ULM_MAX_ANGLES),
+        ("nu", ctypes.c_int32), ("nz", ctypes.c_int32), ("nv", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int32),
+        ("du", ctypes.c_double), ("dz", ctypes.c_double), ("u0", ctypes.c_double),
+        ("z0", ctypes.c_double), ("dv", ctypes.c_double), ("v0", ctypes.c_double),
+        ("v_ref", ctypes.c_double),
+        ("svd_cutoff", ctypes.c_int32), ("ncc_size", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sigma_u", ctypes.c_double), ("sigma_z", ctypes.c_double),
+        ("tau_ncc", ctypes.c_double), ("alpha", ctypes.c_double),
+    ]
+
+
+class ULMTiming(ctypes.Structure):
+    _fields_ = [("ms_beamform", ctypes.c_float), ("ms_filter", ctypes.c_float),
+                ("ms_localize", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+
+# ulm_loc_t: int32 plane, frame, iz, iu; float32 z, u, ncc, intensity (32 bytes)
+LOC_DTYPE = np.dtype([("plane", np.int32), ("frame", np.int32), ("iz", np.int32),
+                      ("iu", np.int32), ("z", np.float32), ("u", np.float32),
+                      ("ncc", np.float32), ("intensity", np.float32)])
+LOC_WORDS = 8
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "ulm_last_error": ([], ctypes.c_char_p),
+        "ulm_create": ([ctypes.POINTER(ULMConfig), ctypes.POINTER(vp)], i32),
+        "ulm_destroy": ([vp], i32),
+        "ulm_workspace_size": ([vp, ctypes.POINTER(sz)], i32),
+        "rca_beamform_proj": ([vp, vp, vp, vp, sz, vp], i32),
+        "rca_beamform_stage1": ([vp, vp, vp, sz, vp], i32),
+        "rca_beamform_stage2": ([vp, vp, vp, sz, vp], i32),
+        "svd_clutter_filter": ([vp, vp, vp, vp, sz, vp], i32),
+        "ncc_localize": ([vp, vp, vp, i32, vp, vp, sz, vp], i32),
+        "ulm_reconstruct_ensemble": ([vp, vp, vp, vp, vp, i32, vp, vp, sz,
+                                      ctypes.POINTER(ULMTiming), vp], i32),
+        "ulm_check_status": ([vp, vp, vp, i32, vp], i32),
+        "ulm_sim_channel_data": ([vp, vp, vp, i32, ctypes.c_uint64, ctypes.c_double, vp, vp], i32),
+        "ulm_density_accumulate": ([vp, vp, vp, i32, i32, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def last_error() -> str:
+    return _lib.ulm_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != ULM_OK:
+        raise ULMError(rc, last_error())
+
+
+def make_config(cfg, precision: int = ULM_PREC_FP64GRAM) -> ULMConfig:
+    """ulm_config_t from a configuration object with probe/seq/grid/loc attributes."""
+    c = ULMConfig()
+    pr, sq, g, lo = cfg.probe, cfg.seq, cfg.grid, cfg.loc
+    angles = [math.radians(a) for a in sq.angles_deg]
+    if len(angles) > ULM_MAX_ANGLES:
+        raise ValueError("too many angles")
+    c.n_elem, c.n_samp, c.n_frames, c.n_angles = pr.n_elem, sq.n_samp, sq.n_frames, len(angles)
+    c.pitch, c.c, c.f0, c.fs = pr.pitch, pr.c, pr.f0, pr.fs
+    c.t_start, c.bandwidth = sq.t_start, pr.bandwidth
+    for i, a in enumerate(angles):
+        c.angles_rad[i] = a
+    c.nu, c.nz, c.nv, c.n_blocks = g.nu, g.nz, g.nv, g.n_blocks
+    c.du, c.dz, c.u0, c.z0, c.dv, c.v0, c.v_ref = g.du, g.dz, g.u0, g.z0, g.dv, g.v0, g.v_ref
+    c.svd_cutoff = cfg.svd_cutoff
+    c.ncc_size = lo.ncc_size
+    c.precision = precision
+    c.sigma_u, c.sigma_z, c.tau_ncc, c.alpha = lo.sigma_u, lo.sigma_z, lo.tau_ncc, lo.alpha
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context plus its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, cfg, precision: int = ULM_PREC_FP64GRAM, device=None):
+        torch = _torch()
+        self.cfg = cfg
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.c = make_config(cfg, precision)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.ulm_create(ctypes.byref(self.c), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_size_t()
+        _check(_lib.ulm_workspace_size(h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+
+    @property
+    def proj_shape(self):
+        c = self.c
+        return (2, c.n_blocks, c.n_frames, c.nz, c.nu)
+
+    @property
+    def iq_shape(self):
+        c = self.c
+        return (c.n_frames, 2, c.n_angles, c.n_elem, c.n_samp)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.ulm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _require(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ULMError(ULM_ERR_INVALID_ARG, f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ULMError(ULM_ERR_INVALID_ARG,
+                       f"{name}: expected contiguous {dtype} {tuple(shape)}, got {t.dtype} "
+                       f"{tuple(t.shape)}")
+
+
+def rca_beamform_proj(ctx: Context, iq, proj=None, stream=None):
+    """IQ [F][2][K][Nc][Ns] complex64 -> projections [2][B][F][Nz][Nu] complex64."""
+    torch = _torch()
+    _require(iq, torch.complex64, ctx.iq_shape, "iq")
+    if proj is None:
+        proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=iq.device)
+    _require(proj, torch.complex64, ctx.proj_shape, "proj")
+    _check(_lib.rca_beamform_proj(ctx.handle, _ptr(iq), _ptr(proj), ctx.ws_ptr, ctx.ws_bytes,
+                                  _stream(stream)))
+    return proj
+
+
+def rca_beamform_stage1(ctx: Context, iq, stream=None):
+    """Stage 1 only: reference slices into the context's workspace."""
+    torch = _torch()
+    _require(iq, torch.complex64, ctx.iq_shape, "iq")
+    _check(_lib.rca_beamform_stage1(ctx.handle, _ptr(iq), ctx.ws_ptr, ctx.ws_bytes,
+                                    _stream(stream)))
+
+
+def rca_beamform_stage2(ctx: Context, proj=None, stream=None):
+    """Stage 2 only: projections from the reference slices held in the workspace."""
+    torch = _torch()
+    if proj is None:
+        proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=ctx.device)
+    _require(proj, torch.complex64, ctx.proj_shape, "proj")
+    _check(_lib.rca_beamform_stage2(ctx.handle, _ptr(proj), ctx.ws_ptr, ctx.ws_bytes,
+                                    _stream(stream)))
+    return proj
+
+
+def svd_clutter_filter(ctx: Context, proj, eigvals=None, stream=None):
+    """In-place clutter filter of every plane; returns eigenvalues [2][B][F] (descending)."""
+    torch = _torch()
+    _require(proj, torch.complex64, ctx.proj_shape, "proj")
+    if eigvals is None:
+        eigvals = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device=proj.device)
+    _require(eigvals, torch.float64, ctx.proj_shape[:3], "eigvals")
+    _check(_lib.svd_clutter_filter(ctx.handle, _ptr(proj), _ptr(eigvals), ctx.ws_ptr,
+                                   ctx.ws_bytes, _stream(stream)))
+    return eigvals
+
+
+def ncc_localize(ctx: Context, filtered, capacity: int, locs=None, count=None, stream=None):
+    """Returns (locs int32 [capacity][8] holding ulm_loc_t records, count int32 [1])."""
+    torch = _torch()
+    _require(filtered, torch.complex64, ctx.proj_shape, "filtered")
+    if locs is None:
+        locs = torch.empty((max(capacity, 1), LOC_WORDS), dtype=torch.int32, device=filtered.device)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=filtered.device)
+    _check(_lib.ncc_localize(ctx.handle, _ptr(filtered), _ptr(locs), int(capacity), _ptr(count),
+                             ctx.ws_ptr, ctx.ws_bytes, _stream(stream)))
+    return locs, count
+
+
+def ulm_reconstruct_ensemble(ctx: Context, iq, capacity: int, proj=None, eigvals=None, locs=None,
+                             count=None, timing: bool = False, stream=None):
+    """The whole path.  Returns dict(proj=filtered planes, eigvals, locs, count, timing)."""
+    torch = _torch()
+    _require(iq, torch.complex64, ctx.iq_shape, "iq")
+    dev = iq.device
+    if proj is None:
+        proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=dev)
+    if eigvals is None:
+        eigvals = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device=dev)
+    if locs is None:
+        locs = torch.empty((max(capacity, 1), LOC_WORDS), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=dev)
+    tm = ULMTiming() if timing else None
+    _check(_lib.ulm_reconstruct_ensemble(ctx.handle, _ptr(iq), _ptr(proj), _ptr(eigvals),
+                                         _ptr(locs), int(capacity), _ptr(count), ctx.ws_ptr,
+                                         ctx.ws_bytes, ctypes.byref(tm) if tm else None,
+                                         _stream(stream)))
+    out = {"proj": proj, "eigvals": eigvals, "locs": locs, "count": count}
+    if tm is not None:
+        out["timing"] = {"beamform": tm.ms_beamform, "filter": tm.ms_filter,
+                         "localize": tm.ms_localize, "total": tm.ms_total}
+    return out
+
+
+def ulm_check_status(ctx: Context, count=None, capacity: int = -1, stream=None):
+    """Synchronise and raise ULMError for a numeric failure or a capacity overflow."""
+    _check(_lib.ulm_check_status(ctx.handle, ctx.ws_ptr,
+                                 _ptr(count) if count is not None else None, int(capacity),
+                                 _stream(stream)))
+
+
+def ulm_sim_channel_data(ctx: Context, pos, amp, noise_seed: int, noise_sigma: float, iq=None,
+                         stream=None):
+    """pos [F][S][3] float64, amp [S] complex128 (device) -> IQ [F][2][K][Nc][Ns] complex64."""
+    torch = _torch()
+    S = pos.shape[1]
+    _require(pos, torch.float64, (ctx.c.n_frames, S, 3), "pos")
+    _require(amp, torch.complex128, (S,), "amp")
+    if iq is None:
+        iq = torch.empty(ctx.iq_shape, dtype=torch.complex64, device=pos.device)
+    _require(iq, torch.complex64, ctx.iq_shape, "iq")
+    _check(_lib.ulm_sim_channel_data(ctx.handle, _ptr(pos), _ptr(amp), int(S),
+                                     ctypes.c_uint64(int(noise_seed) & (2 ** 64 - 1)),
+                                     float(noise_sigma), _ptr(iq), _stream(stream)))
+    return iq
+
+
+def ulm_density_accumulate(ctx: Context, locs, count, capacity: int, density, upsample: int = 2,
+                           stream=None):
+    """Adds the localisations to density [2B][Nz*up][Nu*up] uint32 (torch.int32 storage)."""
+    torch = _torch()
+    shape = (2 * ctx.c.n_blocks, ctx.c.nz * upsample, ctx.c.nu * upsample)
+    _require(density, torch.int32, shape, "density")
+    _check(_lib.ulm_density_accumulate(ctx.handle, _ptr(locs), _ptr(count), int(capacity),
+                                       int(upsample), _ptr(density), _stream(stream)))
+    return density
+
+
+def locs_to_numpy(locs, count) -> np.ndarray:
+    """Copy the first min(count, capacity) records to a structured numpy array."""
+    n = int(count.item()) if hasattr(count, "item") else int(count)
+    n = min(n, locs.shape[0])
+    raw = locs[:n].contiguous().cpu().numpy()
+    return raw.view(LOC_DTYPE).reshape(-1)

@@ -1,0 +1,416 @@
+// C ABI of libulmproj: configuration checks, per-geometry tables (computed on
+// the host in FP64), workspace layout and the entry points.
+#include "common.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace ulm {
+hipError_t launch_stage1(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st);
+hipError_t launch_stage2(const ulm_ctx *ctx, const float2 *slices, float2 *proj, hipStream_t st);
+hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, char *ws,
+                         hipStream_t st);
+hipError_t launch_localize(const ulm_ctx *ctx, const float2 *filt, ulm_loc_t *locs, int capacity,
+                           int *count, char *ws, hipStream_t st);
+hipError_t launch_density(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
+                          int capacity, int up, uint32_t *dens, hipStream_t st);
+hipError_t launch_sim(const ulm_ctx *ctx, const double *pos, const double *amp, int n_scat,
+                      uint64_t seed, double noise_sigma, float *iq, const double *angles_dev,
+                      hipStream_t st);
+size_t ncc_lds_bytes(int nu, int half);
+}  // namespace ulm
+
+using namespace ulm;
+
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+static int32_t hip_fail(hipError_t e, const char *where) {
+    return fail(ULM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                     \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+extern "C" const char *ulm_last_error(void) { return g_err.c_str(); }
+
+// Sample window of the stage-1 beamformer: every pixel of a tile must find
+// floor(s) and floor(s) + 1 inside the kDasLen samples staged from
+// floor(s_min) - 1, where s_min is taken at the tile's shallowest row and the
+// column nearest to the element.  Checked in FP64 with a margin.
+static bool das_window_fits(const ulm_config_t &c, const std::vector<double> &stx, double *worst) {
+    const int n_tu = cdiv(c.nu, kDasTileU), n_tz = cdiv(c.nz, kDasTileZ);
+    double w = 0.0;
+    const double fs_c = c.fs / c.c;
+    for (int k = 0; k < c.n_angles; ++k)
+        for (int tz = 0; tz < n_tz; ++tz) {
+            const int l0 = tz * kDasTileZ, l1 = std::min(l0 + kDasTileZ, c.nz) - 1;
+            const double z0 = c.z0 + l0 * c.dz, z1 = c.z0 + l1 * c.dz;
+            for (int tu = 0; tu < n_tu; ++tu) {
+                const int i0 = tu * kDasTileU, i1 = std::min(i0 + kDasTileU, c.nu) - 1;
+                const double ua = c.u0 + i0 * c.du, ub = c.u0 + i1 * c.du;
+                for (int j = 0; j < c.n_elem; ++j) {
+                    const double ej = (j - 0.5 * (c.n_elem - 1)) * c.pitch;
+                    const double un = std::min(std::max(ej, ua), ub);
+                    const double uf = fabs(ua - ej) > fabs(ub - ej) ? ua : ub;
+                    const double smin = hypot(un - ej, z0) * fs_c + stx[k * c.nz + l0];
+                    const double smax = hypot(uf - ej, z1) * fs_c + stx[k * c.nz + l1];
+                    w = std::max(w, smax - smin);
+                }
+            }
+        }
+    *worst = w;
+    // staged: floor(smin) - 1 ... ; needed up to floor(smax) + 1, plus one sample of margin
+    return w + 4.0 <= (double)(kDasLen - 1);
+}
+
+static int32_t validate(const ulm_config_t &c) {
+    if (c.n_elem < 1 || c.n_samp < 2 || c.n_frames < 1) return fail(ULM_ERR_INVALID_ARG, "n_elem, n_samp, n_frames");
+    if (c.n_angles < 1 || c.n_angles > ULM_MAX_ANGLES) return fail(ULM_ERR_INVALID_ARG, "n_angles out of [1, 32]");
+    if (c.n_frames > 1024) return fail(ULM_ERR_INVALID_ARG, "n_frames > 1024");
+    if (c.nu < 1 || c.nz < 1 || c.nv < 1 || c.n_blocks < 1 || c.n_blocks > c.nv)
+        return fail(ULM_ERR_INVALID_ARG, "grid sizes");
+    if (!(c.pitch > 0 && c.c > 0 && c.f0 > 0 && c.fs > 0 && c.du > 0 && c.dz > 0 && c.dv > 0))
+        return fail(ULM_ERR_INVALID_ARG, "non-positive physical constant");
+    if (c.svd_cutoff < 0 || c.svd_cutoff > 32 || c.svd_cutoff > c.n_frames)
+        return fail(ULM_ERR_INVALID_ARG, "svd_cutoff out of [0, min(32, n_frames)]");
+    if (c.ncc_size < 3 || c.ncc_size > 2 * kNccMaxHalf + 1 || (c.ncc_size & 1) == 0)
+        return fail(ULM_ERR_INVALID_ARG, "ncc_size must be odd in [3, 15]");
+    if (!(c.sigma_u > 0 && c.sigma_z > 0)) return fail(ULM_ERR_INVALID_ARG, "template sigma");
+    if (c.precision != ULM_PREC_FP64GRAM && c.precision != ULM_PREC_BF16X3)
+        return fail(ULM_ERR_INVALID_ARG, "precision");
+    for (int k = 0; k < c.n_angles; ++k)
+        if (!(fabs(c.angles_rad[k]) < 1.2)) return fail(ULM_ERR_INVALID_ARG, "steering angle");
+    if (c.z0 <= 0) return fail(ULM_ERR_INVALID_ARG, "z0 must be positive");
+    if (ncc_lds_bytes(c.nu, (c.ncc_size - 1) / 2) > 160 * 1024)
+        return fail(ULM_ERR_INVALID_ARG, "nu too large for the NCC band tile");
+    if ((size_t)2 * 8 * c.n_samp * sizeof(float) > 160 * 1024)
+        return fail(ULM_ERR_INVALID_ARG, "n_samp too large for the simulator");
+    return ULM_OK;
+}
+
+static void layout_workspace(ulm_ctx *ctx) {
+    const ulm_config_t &c = ctx->cfg;
+    Workspace &w = ctx->ws;
+    const size_t F = c.n_frames, planes = 2 * (size_t)c.n_blocks, npix = (size_t)c.nz * c.nu;
+    const int nblk = cdiv(c.n_frames, kGramBlock);
+    w.gram_pairs = nblk * (nblk + 1) / 2;
+    w.gram_chunks = cdiv((int)npix, kGramChunk);
+    w.bands = cdiv(c.nz, kNccBand);
+    w.band_cap = cdiv(kNccBand, 2) * cdiv(c.nu, 2);
+    const size_t cc = std::max(1, c.svd_cutoff);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    w.slices = take(sizeof(float2) * 2 * c.n_angles * F * npix);
+    w.gram_part = take(sizeof(double2) * planes * w.gram_pairs * w.gram_chunks * kGramBlock * kGramBlock);
+    w.cov = take(sizeof(double2) * planes * F * F);
+    w.tau = take(sizeof(double2) * planes * F);
+    w.diag = take(sizeof(double) * planes * F);
+    w.offd = take(sizeof(double) * planes * F);
+    w.evals = take(sizeof(double) * planes * F);
+    w.evecs = take(sizeof(double2) * planes * F * cc);
+    w.tscratch = take(sizeof(double) * planes * cc * 6 * F);
+    w.xscratch = take(sizeof(double2) * planes * cc * F);
+    w.fmax = take(sizeof(float) * planes * F);
+    w.band_cnt = take(sizeof(int) * planes * F * w.bands);
+    w.band_off = take(sizeof(int) * planes * F * w.bands);
+    w.staged = take(sizeof(ulm_loc_t) * planes * F * w.bands * w.band_cap);
+    w.status = take(sizeof(int) * 4);
+    w.total = off;
+}
+
+extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
+    if (!cfg || !out) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    int32_t rc = validate(*cfg);
+    if (rc != ULM_OK) return rc;
+    const ulm_config_t &c = *cfg;
+
+    // stage-1 transmit delay (in samples, relative to t_start) and per-depth phase
+    const double L = (c.n_elem - 1) * c.pitch;
+    std::vector<double> stx_d((size_t)c.n_angles * c.nz);
+    std::vector<float> stx((size_t)c.n_angles * c.nz);
+    std::vector<float2> phz((size_t)c.n_angles * c.nz);
+    for (int k = 0; k < c.n_angles; ++k) {
+        const double th = c.angles_rad[k];
+        for (int l = 0; l < c.nz; ++l) {
+            const double z = c.z0 + l * c.dz;
+            const double ttx = (z * cos(th) + c.v_ref * sin(th) + 0.5 * L * fabs(sin(th))) / c.c;
+            stx_d[k * c.nz + l] = (ttx - c.t_start) * c.fs;
+            stx[k * c.nz + l] = (float)stx_d[k * c.nz + l];
+            double cyc = c.f0 * (ttx - z / c.c);
+            cyc -= nearbyint(cyc);
+            phz[k * c.nz + l] = make_float2((float)cos(2 * M_PI * cyc), (float)sin(2 * M_PI * cyc));
+        }
+    }
+    double worst = 0;
+    if (!das_window_fits(c, stx_d, &worst)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "delay span of a beamforming tile (%.1f samples) exceeds the %d-sample window",
+                 worst, kDasLen);
+        return fail(ULM_ERR_INVALID_ARG, buf);
+    }
+
+    // stage-2 axial taps per (transmit, block): H[d] = sum_m exp(i phi_m) Lambda(d_m - d)
+    const int per = cdiv(c.nv, c.n_blocks);
+    int dmin = 0, dmax = 0;
+    std::vector<std::vector<std::complex<double>>> acc((size_t)c.n_angles * c.n_blocks);
+    std::vector<int> acc_lo((size_t)c.n_angles * c.n_blocks);
+    const int span = 4 * (c.nz + 8);
+    for (int k = 0; k < c.n_angles; ++k) {
+        const double tk = tan(0.5 * c.angles_rad[k]);
+        for (int b = 0; b < c.n_blocks; ++b) {
+            auto &h = acc[k * c.n_blocks + b];
+            h.assign(2 * span + 1, 0.0);
+            for (int m = b * per; m < std::min((b + 1) * per, c.nv); ++m) {
+                const double dv = c.v0 + m * c.dv - c.v_ref;
+                const double d = dv * tk / c.dz;
+                const double ph = 4.0 * M_PI * c.f0 * dv * tk / c.c;
+                const double fl = floor(d);
+                const int n = (int)fl;
+                const double fr = d - fl;
+                if (n < -span || n + 1 > span) return fail(ULM_ERR_INVALID_ARG, "stage-2 shift out of range");
+                const std::complex<double> e = std::polar(1.0, ph);
+                h[n + span] += (1.0 - fr) * e;
+                h[n + 1 + span] += fr * e;
+            }
+            for (int q = 0; q <= 2 * span; ++q)
+                if (h[q] != 0.0) {
+                    dmin = std::min(dmin, q - span);
+                    dmax = std::max(dmax, q - span);
+                }
+        }
+    }
+    const int n_taps = dmax - dmin + 1;
+    if (n_taps > kFirMaxTaps) return fail(ULM_ERR_INVALID_ARG, "stage-2 shift needs too many taps");
+    std::vector<float2> taps((size_t)c.n_angles * c.n_blocks * n_taps);
+    for (int kb = 0; kb < c.n_angles * c.n_blocks; ++kb)
+        for (int q = 0; q < n_taps; ++q) {
+            const std::complex<double> v = acc[kb][dmin + q + span];
+            taps[(size_t)kb * n_taps + q] = make_float2((float)v.real(), (float)v.imag());
+        }
+
+    ulm_ctx *ctx = new (std::nothrow) ulm_ctx();
+    if (!ctx) return fail(ULM_ERR_INVALID_ARG, "out of host memory");
+    ctx->cfg = c;
+    Geometry &g = ctx->geo;
+    g.n_elem = c.n_elem;
+    g.n_samp = c.n_samp;
+    g.n_frames = c.n_frames;
+    g.n_angles = c.n_angles;
+    g.nu = c.nu;
+    g.nz = c.nz;
+    g.n_blocks = c.n_blocks;
+    g.n_planes = 2 * c.n_blocks;
+    g.pitch = (float)c.pitch;
+    g.fs_over_c = (float)(c.fs / c.c);
+    g.f0_over_c = (float)(c.f0 / c.c);
+    g.t_start_fs = (float)(c.t_start * c.fs);
+    g.du = (float)c.du;
+    g.dz = (float)c.dz;
+    g.u0 = (float)c.u0;
+    g.z0 = (float)c.z0;
+    ctx->tab.tap_min = dmin;
+    ctx->tab.n_taps = n_taps;
+    layout_workspace(ctx);
+
+    auto cleanup = [&](hipError_t e, const char *where) {
+        (void)hipFree(ctx->tab.stx);
+        (void)hipFree(ctx->tab.phz);
+        (void)hipFree(ctx->tab.taps);
+        (void)hipFree(ctx->tab.angles);
+        delete ctx;
+        return hip_fail(e, where);
+    };
+    hipError_t e;
+    if ((e = hipGetDevice(&ctx->device)) != hipSuccess) return cleanup(e, "hipGetDevice");
+    if ((e = hipMalloc(&ctx->tab.stx, sizeof(float) * stx.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.phz, sizeof(float2) * phz.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.taps, sizeof(float2) * taps.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.angles, sizeof(double) * ULM_MAX_ANGLES)) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMemcpy(ctx->tab.stx, stx.data(), sizeof(float) * stx.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMemcpy(ctx->tab.phz, phz.data(), sizeof(float2) * phz.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMemcpy(ctx->tab.taps, taps.data(), sizeof(float2) * taps.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMemcpy(ctx->tab.angles, c.angles_rad, sizeof(double) * ULM_MAX_ANGLES, hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    int lds_max = 0;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device)) != hipSuccess)
+        return cleanup(e, "hipDeviceGetAttribute");
+    if (ncc_lds_bytes(c.nu, (c.ncc_size - 1) / 2) > (size_t)lds_max ||
+        (size_t)2 * 8 * c.n_samp * sizeof(float) > (size_t)lds_max) {
+        (void)hipFree(ctx->tab.stx);
+        (void)hipFree(ctx->tab.phz);
+        (void)hipFree(ctx->tab.taps);
+        (void)hipFree(ctx->tab.angles);
+        delete ctx;
+        return fail(ULM_ERR_INVALID_ARG, "plane width or sample count exceeds the device's LDS per work-group");
+    }
+    for (int i = 0; i < 4; ++i)
+        if ((e = hipEventCreate(&ctx->ev[i])) != hipSuccess) return cleanup(e, "hipEventCreate");
+    *out = ctx;
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_destroy(ulm_ctx_t *ctx) {
+    if (!ctx) return ULM_OK;
+    (void)hipFree(ctx->tab.stx);
+    (void)hipFree(ctx->tab.phz);
+    (void)hipFree(ctx->tab.taps);
+    (void)hipFree(ctx->tab.angles);
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ctx->ev[i]);
+    delete ctx;
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_workspace_size(const ulm_ctx_t *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    *bytes = ctx->ws.total;
+    return ULM_OK;
+}
+
+static int32_t check_ws(const ulm_ctx_t *ctx, void *ws, size_t ws_bytes) {
+    if (!ctx) return fail(ULM_ERR_INVALID_ARG, "NULL context");
+    if (!ws) return fail(ULM_ERR_INVALID_ARG, "NULL workspace");
+    if (ws_bytes < ctx->ws.total) return fail(ULM_ERR_INVALID_ARG, "workspace too small");
+    if (((uintptr_t)ws & 255) != 0) return fail(ULM_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    return ULM_OK;
+}
+
+extern "C" int32_t rca_beamform_stage1(ulm_ctx_t *ctx, const float *iq, void *ws, size_t ws_bytes,
+                                       void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!iq) return fail(ULM_ERR_INVALID_ARG, "NULL iq");
+    HIP_TRY(launch_stage1(ctx, (const float2 *)iq, (float2 *)((char *)ws + ctx->ws.slices),
+                          (hipStream_t)stream),
+            "rca_beamform_stage1");
+    return ULM_OK;
+}
+
+extern "C" int32_t rca_beamform_stage2(ulm_ctx_t *ctx, float *proj, void *ws, size_t ws_bytes,
+                                       void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!proj) return fail(ULM_ERR_INVALID_ARG, "NULL proj");
+    HIP_TRY(launch_stage2(ctx, (const float2 *)((char *)ws + ctx->ws.slices), (float2 *)proj,
+                          (hipStream_t)stream),
+            "rca_beamform_stage2");
+    return ULM_OK;
+}
+
+extern "C" int32_t rca_beamform_proj(ulm_ctx_t *ctx, const float *iq, float *proj, void *ws,
+                                     size_t ws_bytes, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!iq || !proj) return fail(ULM_ERR_INVALID_ARG, "NULL iq or proj");
+    if ((rc = rca_beamform_stage1(ctx, iq, ws, ws_bytes, stream))) return rc;
+    return rca_beamform_stage2(ctx, proj, ws, ws_bytes, stream);
+}
+
+extern "C" int32_t svd_clutter_filter(ulm_ctx_t *ctx, float *proj, double *eigvals, void *ws,
+                                      size_t ws_bytes, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!proj) return fail(ULM_ERR_INVALID_ARG, "NULL proj");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_filter(ctx, (float2 *)proj, eigvals, (char *)ws, st), "svd_clutter_filter");
+    return ULM_OK;
+}
+
+extern "C" int32_t ncc_localize(ulm_ctx_t *ctx, const float *filtered, ulm_loc_t *locs,
+                                int32_t capacity, int32_t *count, void *ws, size_t ws_bytes,
+                                void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!filtered || !count || capacity < 0 || (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "NULL filtered/count/locs or negative capacity");
+    HIP_TRY(launch_localize(ctx, (const float2 *)filtered, locs, capacity, count, (char *)ws,
+                            (hipStream_t)stream),
+            "ncc_localize");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_reconstruct_ensemble(ulm_ctx_t *ctx, const float *iq, float *proj,
+                                            double *eigvals, ulm_loc_t *locs, int32_t capacity,
+                                            int32_t *count, void *ws, size_t ws_bytes,
+                                            ulm_timing_t *timing, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!iq || !proj || !count || capacity < 0 || (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    hipStream_t st = (hipStream_t)stream;
+    if (timing) HIP_TRY(hipEventRecord(ctx->ev[0], st), "hipEventRecord");
+    if ((rc = rca_beamform_proj(ctx, iq, proj, ws, ws_bytes, stream))) return rc;
+    if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], st), "hipEventRecord");
+    if ((rc = svd_clutter_filter(ctx, proj, eigvals, ws, ws_bytes, stream))) return rc;
+    if (timing) HIP_TRY(hipEventRecord(ctx->ev[2], st), "hipEventRecord");
+    if ((rc = ncc_localize(ctx, proj, locs, capacity, count, ws, ws_bytes, stream))) return rc;
+    if (timing) {
+        HIP_TRY(hipEventRecord(ctx->ev[3], st), "hipEventRecord");
+        HIP_TRY(hipEventSynchronize(ctx->ev[3]), "hipEventSynchronize");
+        HIP_TRY(hipEventElapsedTime(&timing->ms_beamform, ctx->ev[0], ctx->ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&timing->ms_filter, ctx->ev[1], ctx->ev[2]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&timing->ms_localize, ctx->ev[2], ctx->ev[3]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&timing->ms_total, ctx->ev[0], ctx->ev[3]), "hipEventElapsedTime");
+    }
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_check_status(ulm_ctx_t *ctx, void *ws, const int32_t *count,
+                                    int32_t capacity, void *stream) {
+    if (!ctx || !ws) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    int status = 0;
+    HIP_TRY(hipMemcpy(&status, (char *)ws + ctx->ws.status, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (status & kStatusNumeric) return fail(ULM_ERR_NUMERIC, "non-finite covariance: plane left unfiltered");
+    if (count && capacity >= 0) {
+        int n = 0;
+        HIP_TRY(hipMemcpy(&n, count, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (n > capacity) return fail(ULM_ERR_OVERFLOW, "more localisations than capacity");
+    }
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_sim_channel_data(ulm_ctx_t *ctx, const double *pos, const double *amp,
+                                        int32_t n_scat, uint64_t noise_seed, double noise_sigma,
+                                        float *iq, void *stream) {
+    if (!ctx || !iq || n_scat < 0 || (n_scat > 0 && (!pos || !amp)) || !(noise_sigma >= 0))
+        return fail(ULM_ERR_INVALID_ARG, "bad simulator argument");
+    HIP_TRY(launch_sim(ctx, pos, amp, n_scat, noise_seed, noise_sigma, iq,
+                       ctx->tab.angles, (hipStream_t)stream),
+            "ulm_sim_channel_data");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_density_accumulate(ulm_ctx_t *ctx, const ulm_loc_t *locs,
+                                          const int32_t *count, int32_t capacity,
+                                          int32_t upsample, uint32_t *density, void *stream) {
+    if (!ctx || !count || !density || capacity < 0 || upsample < 1 || upsample > 16 ||
+        (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "bad density argument");
+    HIP_TRY(launch_density(ctx, locs, count, capacity, upsample, density, (hipStream_t)stream),
+            "ulm_density_accumulate");
+    return ULM_OK;
+}

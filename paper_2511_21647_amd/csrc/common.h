@@ -1,0 +1,79 @@
+// Internal definitions shared by the HIP translation units of libulmproj.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ulmproj.h"
+
+namespace ulm {
+
+constexpr int kDasThreads = 256;   // one pixel per thread
+constexpr int kDasTileU = 32;      // tile: 8 rows (z) x 32 columns (u)
+constexpr int kDasTileZ = 8;
+constexpr int kDasFrames = 16;     // frames beamformed per delay evaluation
+constexpr int kDasLen = 128;       // staged samples per channel and frame
+
+constexpr int kFirTileZ = 32;
+constexpr int kFirTileU = 64;
+constexpr int kFirMaxTaps = 48;
+
+constexpr int kGramBlock = 64;     // frames per Gram block (rows and columns)
+constexpr int kGramChunk = 2048;   // pixels reduced by one Gram work-group
+constexpr int kGramStage = 32;     // pixels staged in LDS per step
+
+constexpr int kNccBand = 16;       // NCC output rows per work-group
+constexpr int kNccMaxHalf = 7;     // template half-width limit (size <= 15)
+
+// Status bits written to the workspace status word.
+constexpr int kStatusNumeric = 1;
+
+struct Geometry {
+    int n_elem, n_samp, n_frames, n_angles;
+    int nu, nz, n_blocks, n_planes;
+    float pitch, fs_over_c, f0_over_c, t_start_fs;
+    float du, dz, u0, z0;
+};
+
+// Device tables owned by the context.
+struct Tables {
+    float *stx;        // [K][Nz]   (tau_tx(v_ref, z; k) - t_start) * fs
+    float2 *phz;       // [K][Nz]   exp(i 2 pi f0 (tau_tx - z / c))
+    float2 *taps;      // [K][B][T] stage-2 axial FIR taps
+    double *angles;    // [K]       steering angles (simulator)
+    int tap_min, n_taps;
+};
+
+// Offsets of the workspace regions, in bytes.
+struct Workspace {
+    size_t slices;      // [2][K][F][Nz][Nu] c64    stage-1 reference slices
+    size_t gram_part;   // [planes][pairs][chunks][64][64] c128
+    size_t cov;         // [planes][F][F] c128
+    size_t tau;         // [planes][F] c128         Householder scalars
+    size_t diag;        // [planes][F] f64
+    size_t offd;        // [planes][F] f64
+    size_t evals;       // [planes][F] f64          descending
+    size_t evecs;       // [planes][F][c] c128
+    size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
+    size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
+    size_t fmax;        // [planes][F] f32
+    size_t band_cnt;    // [planes][F][bands] i32
+    size_t band_off;    // [planes][F][bands] i32
+    size_t staged;      // [planes][F][bands][cap] ulm_loc_t
+    size_t status;      // i32
+    size_t total;
+    int gram_pairs, gram_chunks, bands, band_cap;
+};
+
+template <typename T> __host__ __device__ inline T cdiv(T a, T b) { return (a + b - 1) / b; }
+
+}  // namespace ulm
+
+struct ulm_ctx {
+    ulm_config_t cfg;
+    ulm::Geometry geo;
+    ulm::Tables tab;
+    ulm::Workspace ws;
+    int device;
+    hipEvent_t ev[4];
+};

@@ -1,0 +1,309 @@
+// NCC microbubble localisation (paper Section II-A4) on filtered planes.
+//
+//   frame_max_kernel   per-(plane, frame) maximum of the envelope |P|, the
+//                      reference of the intensity threshold
+//   ncc_detect_kernel  one work-group per band of 16 rows x full width: envelope
+//                      tile with halo in LDS, two separable passes (Fig. 1g) of
+//                      three sums (template, box, box of squares), zero-mean NCC,
+//                      3x3 regional maxima with raster tie-break, thresholds,
+//                      3-point Gaussian sub-pixel fit, and an in-band compaction
+//                      in raster order (wave ballots + a block scan)
+//   loc_scan_kernel    exclusive scan of the per-band counts
+//   loc_scatter_kernel copies each band's records to its output offset
+// Output order is (plane, frame, row, column) without any sort: bands are full
+// width and are laid out in that order.
+#include "common.h"
+
+#include <math.h>
+
+namespace ulm {
+
+struct NccParams {
+    int half;             // template half width h
+    float kbar;           // mean of the template
+    float inv_w;          // 1 / size^2
+    float inv_sk;         // 1 / sqrt(sum (K - Kbar)^2)
+    float tau, alpha;
+    float gz[2 * kNccMaxHalf + 1], gu[2 * kNccMaxHalf + 1];
+};
+
+__global__ __launch_bounds__(256) void frame_max_kernel(const float2 *__restrict__ P,
+                                                        float *__restrict__ fmax_out, int npix)
+{
+    const float2 *src = P + (size_t)blockIdx.x * npix;
+    float m = 0.f;
+    for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+        const float2 v = src[i];
+        m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) fmax_out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__device__ inline float subpix(float nm, float n0, float np) {
+    float d;
+    if (nm > 0.f && n0 > 0.f && np > 0.f) {
+        const float lm = logf(nm), l0 = logf(n0), lp = logf(np);
+        const float den = 2.f * (lm - 2.f * l0 + lp);
+        d = den < 0.f ? (lm - lp) / den : 0.f;
+    } else {
+        const float den = 2.f * (nm - 2.f * n0 + np);
+        d = den < 0.f ? (nm - np) / den : 0.f;
+    }
+    return fminf(fmaxf(d, -0.5f), 0.5f);
+}
+
+// Dynamic LDS: img [R_in][W_in] (reused for ncc [kNccBand+2][nu+2]), then
+// Vg, V1, V2 [kNccBand+2][W_in].
+__global__ __launch_bounds__(256) void ncc_detect_kernel(
+    const float2 *__restrict__ P, const float *__restrict__ fmax_in, ulm_loc_t *__restrict__ staged,
+    int *__restrict__ band_cnt, NccParams prm, int nz, int nu, int F, int bands, int band_cap)
+{
+    extern __shared__ float smem[];
+    const int band = blockIdx.x, f = blockIdx.y, plane = blockIdx.z;
+    const int h = prm.half;
+    const int R_out = kNccBand + 2;                 // NCC rows with a halo of 1
+    const int R_in = R_out + 2 * h;
+    const int W_in = nu + 2 + 2 * h;
+    const int W_out = nu + 2;
+    float *img = smem;
+    float *Vg = smem + (size_t)R_in * W_in;
+    float *V1 = Vg + (size_t)R_out * W_in;
+    float *V2 = V1 + (size_t)R_out * W_in;
+    float *ncc = img;                               // after the vertical pass
+
+    const int r0 = band * kNccBand;                 // first output row of the band
+    const float2 *src = P + ((size_t)plane * F + f) * (size_t)nz * nu;
+
+    for (int e = threadIdx.x; e < R_in * W_in; e += blockDim.x) {
+        const int rr = e / W_in, cc = e % W_in;
+        const int z = r0 - 1 - h + rr, u = cc - 1 - h;
+        float v = 0.f;
+        if (z >= 0 && z < nz && u >= 0 && u < nu) {
+            const float2 x = src[(size_t)z * nu + u];
+            v = sqrtf(x.x * x.x + x.y * x.y);
+        }
+        img[e] = v;
+    }
+    __syncthreads();
+    const int S = 2 * h + 1;
+    for (int e = threadIdx.x; e < R_out * W_in; e += blockDim.x) {
+        const int rr = e / W_in, cc = e % W_in;
+        float sg = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int a = 0; a < S; ++a) {
+            const float x = img[(rr + a) * W_in + cc];
+            sg = fmaf(prm.gz[a], x, sg);
+            s1 += x;
+            s2 = fmaf(x, x, s2);
+        }
+        Vg[e] = sg;
+        V1[e] = s1;
+        V2[e] = s2;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R_out * W_out; e += blockDim.x) {
+        const int rr = e / W_out, cc = e % W_out;
+        const int z = r0 - 1 + rr, u = cc - 1;
+        float out = -INFINITY;                      // outside the image: ignored by the peak test
+        if (z >= 0 && z < nz && u >= 0 && u < nu) {
+            float sik = 0.f, si = 0.f, si2 = 0.f;
+            const int base = rr * W_in + cc;
+            for (int b = 0; b < S; ++b) {
+                sik = fmaf(prm.gu[b], Vg[base + b], sik);
+                si += V1[base + b];
+                si2 += V2[base + b];
+            }
+            const float num = sik - prm.kbar * si;
+            const float var = si2 - si * si * prm.inv_w;
+            out = var > 1e-6f * si2 ? num * prm.inv_sk * rsqrtf(var) : 0.f;
+        }
+        ncc[e] = out;
+    }
+    __syncthreads();
+
+    // detection + raster-order compaction within the band
+    __shared__ int wave_tot[4];
+    __shared__ int base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    const float thr_i = prm.alpha * fmax_in[plane * F + f];
+    const int rows = min(kNccBand, nz - r0);
+    const int npx = rows * nu;
+    ulm_loc_t *out = staged + ((size_t)(plane * F + f) * bands + band) * band_cap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e0 = 0; e0 < npx; e0 += blockDim.x) {
+        const int e = e0 + threadIdx.x;
+        bool cand = false;
+        ulm_loc_t rec;
+        if (e < npx) {
+            const int rr = e / nu + 1, cc = e % nu + 1;      // position in the ncc array
+            const float n0 = ncc[rr * W_out + cc];
+            const int z = r0 + rr - 1, u = cc - 1;
+            if (n0 >= prm.tau) {
+                const float2 x = src[(size_t)z * nu + u];
+                const float I = sqrtf(x.x * x.x + x.y * x.y);
+                if (I >= thr_i) {
+                    const float *up = ncc + (rr - 1) * W_out + cc;
+                    const float *mid = ncc + rr * W_out + cc;
+                    const float *dn = ncc + (rr + 1) * W_out + cc;
+                    cand = n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] &&
+                           n0 >= mid[1] && n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
+                    if (cand) {
+                        const float dz = (z > 0 && z < nz - 1) ? subpix(up[0], n0, dn[0]) : 0.f;
+                        const float du = (u > 0 && u < nu - 1) ? subpix(mid[-1], n0, mid[1]) : 0.f;
+                        rec.plane = plane;
+                        rec.frame = f;
+                        rec.iz = z;
+                        rec.iu = u;
+                        rec.z = (float)z + dz;
+                        rec.u = (float)u + du;
+                        rec.ncc = n0;
+                        rec.intensity = I;
+                    }
+                }
+            }
+        }
+        const unsigned long long bal = __ballot(cand);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base_s;
+        for (int q = 0; q < wv; ++q) off += wave_tot[q];
+        if (cand) out[off + pre] = rec;
+        __syncthreads();
+        if (threadIdx.x == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) band_cnt[(plane * F + f) * bands + band] = base_s;
+}
+
+// Exclusive scan of n counts by one work-group; writes the total to *count.
+__global__ __launch_bounds__(1024) void loc_scan_kernel(const int *__restrict__ cnt,
+                                                        int *__restrict__ off, int n,
+                                                        int *__restrict__ count)
+{
+    __shared__ int s[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < n; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < n ? cnt[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int x = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (i < n) off[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(256) void loc_scatter_kernel(
+    const ulm_loc_t *__restrict__ staged, const int *__restrict__ cnt, const int *__restrict__ off,
+    ulm_loc_t *__restrict__ locs, int capacity, int band_cap)
+{
+    const int slot = blockIdx.x;
+    const int n = cnt[slot], o = off[slot];
+    const ulm_loc_t *src = staged + (size_t)slot * band_cap;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (o + i < capacity) locs[o + i] = src[i];
+}
+
+__global__ void density_kernel(const ulm_loc_t *__restrict__ locs, const int *__restrict__ count,
+                               int capacity, int up, int nz, int nu, int planes,
+                               uint32_t *__restrict__ dens)
+{
+    const int n = min(*count, capacity);
+    const int W = nu * up, H = nz * up;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const ulm_loc_t r = locs[i];
+        const int bz = (int)floorf((r.z + 0.5f) * up);
+        const int bu = (int)floorf((r.u + 0.5f) * up);
+        if (r.plane < 0 || r.plane >= planes || bz < 0 || bz >= H || bu < 0 || bu >= W) continue;
+        atomicAdd(&dens[((size_t)r.plane * H + bz) * W + bu], 1u);
+    }
+}
+
+size_t ncc_lds_bytes(int nu, int half) {
+    const size_t R_out = kNccBand + 2, R_in = R_out + 2 * half, W_in = nu + 2 + 2 * half;
+    const size_t img = std::max(R_in * W_in, R_out * (size_t)(nu + 2));
+    return (img + 3 * R_out * W_in) * sizeof(float);
+}
+
+NccParams make_ncc_params(const ulm_ctx *ctx) {
+    const ulm_config_t &c = ctx->cfg;
+    NccParams p{};
+    const int h = (c.ncc_size - 1) / 2;
+    p.half = h;
+    double sz = 0, su = 0;
+    double gz[2 * kNccMaxHalf + 1], gu[2 * kNccMaxHalf + 1];
+    for (int a = -h; a <= h; ++a) {
+        gz[a + h] = exp(-(double)a * a / (2.0 * c.sigma_z * c.sigma_z));
+        gu[a + h] = exp(-(double)a * a / (2.0 * c.sigma_u * c.sigma_u));
+        sz += gz[a + h];
+        su += gu[a + h];
+        p.gz[a + h] = (float)gz[a + h];
+        p.gu[a + h] = (float)gu[a + h];
+    }
+    const double W = (double)c.ncc_size * c.ncc_size;
+    const double kbar = sz * su / W;
+    double sk = 0;
+    for (int a = 0; a < c.ncc_size; ++a)
+        for (int b = 0; b < c.ncc_size; ++b) {
+            const double d = gz[a] * gu[b] - kbar;
+            sk += d * d;
+        }
+    p.kbar = (float)kbar;
+    p.inv_w = (float)(1.0 / W);
+    p.inv_sk = (float)(1.0 / sqrt(sk));
+    p.tau = (float)c.tau_ncc;
+    p.alpha = (float)c.alpha;
+    return p;
+}
+
+hipError_t launch_localize(const ulm_ctx *ctx, const float2 *filt, ulm_loc_t *locs, int capacity,
+                           int *count, char *ws, hipStream_t st)
+{
+    const Geometry &g = ctx->geo;
+    const Workspace &w = ctx->ws;
+    const int npix = g.nz * g.nu, F = g.n_frames, planes = g.n_planes;
+    float *fmx = (float *)(ws + w.fmax);
+    int *bcnt = (int *)(ws + w.band_cnt);
+    int *boff = (int *)(ws + w.band_off);
+    ulm_loc_t *staged = (ulm_loc_t *)(ws + w.staged);
+    hipLaunchKernelGGL(frame_max_kernel, dim3(planes * F), dim3(256), 0, st, filt, fmx, npix);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const NccParams prm = make_ncc_params(ctx);
+    const size_t lds = ncc_lds_bytes(g.nu, prm.half);
+    hipLaunchKernelGGL(ncc_detect_kernel, dim3(w.bands, F, planes), dim3(256), lds, st, filt, fmx,
+                       staged, bcnt, prm, g.nz, g.nu, F, w.bands, w.band_cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nslots = planes * F * w.bands;
+    hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(1024), 0, st, bcnt, boff, nslots, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(loc_scatter_kernel, dim3(nslots), dim3(256), 0, st, staged, bcnt, boff,
+                       locs, capacity, w.band_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
+                          int capacity, int up, uint32_t *dens, hipStream_t st)
+{
+    const Geometry &g = ctx->geo;
+    hipLaunchKernelGGL(density_kernel, dim3(1024), dim3(256), 0, st, locs, count, capacity, up,
+                       g.nz, g.nu, g.n_planes, dens);
+    return hipGetLastError();
+}
+
+
+}  // namespace ulm

@@ -1,0 +1,681 @@
+// Eigen-based SVD clutter filter (paper Section II-A2) of each projection
+// plane's Casorati matrix I (pixels x frames):
+//   1. covariance C = I^H I   (gram_f64_kernel + gram_reduce_kernel, FP64 MFMA;
+//      gram_bf16x3_kernel for the split-precision form)
+//   2. eigendecomposition of C in FP64 (eigen_kernel: Householder
+//      tridiagonalisation, bisection on Sturm counts, inverse iteration for the
+//      clutter eigenvectors, back-transformation)
+//   3. removal I_f = I - (I V_c) V_c^H   (removal_kernel, FP64 accumulation)
+// Layout: a plane is stored frame-major, [F][n_pix] complex64, i.e. the
+// transpose of the Casorati matrix; the frame axis is the Gram's output axis
+// and the pixel axis its reduction axis.
+#include "common.h"
+
+#include <float.h>
+
+namespace ulm {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline void pair_of(int pair, int nblk, int &I, int &J) {
+    int p = pair;
+    for (I = 0; I < nblk; ++I) {
+        const int n = nblk - I;
+        if (p < n) { J = I + p; return; }
+        p -= n;
+    }
+    I = J = 0;
+}
+
+// ---------------------------------------------------------------- Gram, FP64 MFMA
+// One work-group: one plane, one 64x64 block pair (I <= J) of C, one chunk of
+// pixels.  Four waves, each a 32x32 quadrant = 2x2 tiles of
+// v_mfma_f64_16x16x4f64.  K = 4 per instruction = 2 pixels x (re, im):
+//   C_re += A . B      with A[f][k], B[k][f'] = (re, im) of pixel p
+//   C_im += A . B'     with B'[k][f'] = (im, -re)
+// FP32 inputs are exact in FP64, so every product is exact and only FP64
+// summation rounds.
+__global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict__ P,
+                                                       double2 *__restrict__ part, int F,
+                                                       int npix, int pairs, int chunks, int nblk)
+{
+    const int chunk = blockIdx.x % chunks;
+    const int pair = (blockIdx.x / chunks) % pairs;
+    const int plane = blockIdx.x / (chunks * pairs);
+    int I, J;
+    pair_of(pair, nblk, I, J);
+    const float2 *src = P + (size_t)plane * F * npix;
+    const int px0 = chunk * kGramChunk;
+    const int px1 = min(px0 + kGramChunk, npix);
+
+    __shared__ float2 lds[2 * kGramBlock][kGramStage + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int kk = lane >> 4, r16 = lane & 15;
+
+    f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            accr[a][b] = f64x4{0, 0, 0, 0};
+            acci[a][b] = f64x4{0, 0, 0, 0};
+        }
+
+    for (int p0 = px0; p0 < px1; p0 += kGramStage) {
+        for (int e = threadIdx.x; e < 2 * kGramBlock * kGramStage; e += 256) {
+            const int row = e / kGramStage, col = e % kGramStage;
+            const int frame = row < kGramBlock ? I * kGramBlock + row : J * kGramBlock + row - kGramBlock;
+            const int px = p0 + col;
+            float2 v = make_float2(0.f, 0.f);
+            if (frame < F && px < px1) v = src[(size_t)frame * npix + px];
+            lds[row][col] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int step = 0; step < kGramStage / 2; ++step) {
+            const int pxl = step * 2 + (kk >> 1);
+            const bool im = kk & 1;
+            double a[2], br[2], bi[2];
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti) {
+                const float2 v = lds[wi * 32 + ti * 16 + r16][pxl];
+                a[ti] = im ? v.y : v.x;
+            }
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) {
+                const float2 v = lds[kGramBlock + wj * 32 + tj * 16 + r16][pxl];
+                br[tj] = im ? v.y : v.x;
+                bi[tj] = im ? -v.x : v.y;
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) {
+                    accr[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], br[tj], accr[ti][tj], 0, 0, 0);
+                    acci[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], bi[tj], acci[ti][tj], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+
+    double2 *dst = part + ((size_t)(plane * pairs + pair) * chunks + chunk) * kGramBlock * kGramBlock;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wi * 32 + ti * 16 + 4 * kk + r;
+                const int col = wj * 32 + tj * 16 + r16;
+                dst[row * kGramBlock + col] = make_double2(accr[ti][tj][r], acci[ti][tj][r]);
+            }
+}
+
+// ---------------------------------------------------------------- Gram, BF16 split
+// Split-precision form: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the
+// products hi.hi + hi.lo + lo.hi run on v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation.  The FP32 accumulators are folded into FP64 after every staged
+// group of pixels.  One wave per 32x32 quadrant; K = 16 = 8 pixels x (re, im).
+__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+
+__global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float2 *__restrict__ P,
+                                                          double2 *__restrict__ part, int F,
+                                                          int npix, int pairs, int chunks, int nblk)
+{
+    const int chunk = blockIdx.x % chunks;
+    const int pair = (blockIdx.x / chunks) % pairs;
+    const int plane = blockIdx.x / (chunks * pairs);
+    int I, J;
+    pair_of(pair, nblk, I, J);
+    const float2 *src = P + (size_t)plane * F * npix;
+    const int px0 = chunk * kGramChunk;
+    const int px1 = min(px0 + kGramChunk, npix);
+
+    __shared__ float2 lds[2 * kGramBlock][kGramStage + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int half = lane >> 5, r32 = lane & 31;
+
+    double dr[16], di[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dr[q] = di[q] = 0.0;
+
+    for (int p0 = px0; p0 < px1; p0 += kGramStage) {
+        for (int e = threadIdx.x; e < 2 * kGramBlock * kGramStage; e += 256) {
+            const int row = e / kGramStage, col = e % kGramStage;
+            const int frame = row < kGramBlock ? I * kGramBlock + row : J * kGramBlock + row - kGramBlock;
+            const int px = p0 + col;
+            float2 v = make_float2(0.f, 0.f);
+            if (frame < F && px < px1) v = src[(size_t)frame * npix + px];
+            lds[row][col] = v;
+        }
+        __syncthreads();
+        f32x16 cr = {}, ci = {};
+#pragma unroll
+        for (int step = 0; step < kGramStage / 8; ++step) {
+            // lane holds k = half*8 + [0, 8): pixels step*8 + half*4 + [0, 4), (re, im) each
+            bf16x8 ahi, alo, bhi, blo, bihi, bilo;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pxl = step * 8 + half * 4 + q;
+                const float2 va = lds[wi * 32 + r32][pxl];
+                const float2 vb = lds[kGramBlock + wj * 32 + r32][pxl];
+                const __bf16 ar = to_bf16(va.x), ai = to_bf16(va.y);
+                const __bf16 br = to_bf16(vb.x), bi = to_bf16(vb.y);
+                ahi[2 * q] = ar;  alo[2 * q] = to_bf16(va.x - (float)ar);
+                ahi[2 * q + 1] = ai;  alo[2 * q + 1] = to_bf16(va.y - (float)ai);
+                bhi[2 * q] = br;  blo[2 * q] = to_bf16(vb.x - (float)br);
+                bhi[2 * q + 1] = bi;  blo[2 * q + 1] = to_bf16(vb.y - (float)bi);
+                // B' = (im, -re)
+                bihi[2 * q] = bi;  bilo[2 * q] = blo[2 * q + 1];
+                bihi[2 * q + 1] = to_bf16(-vb.x);  bilo[2 * q + 1] = to_bf16(-(vb.x - (float)br));
+            }
+            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bihi, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bilo, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bihi, ci, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) { dr[q] += cr[q]; di[q] += ci[q]; }
+        __syncthreads();
+    }
+
+    double2 *dst = part + ((size_t)(plane * pairs + pair) * chunks + chunk) * kGramBlock * kGramBlock;
+    // 32x32 output layout: acc q -> row 8*(q/4) + 4*half + q%4, column r32
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int row = wi * 32 + 8 * (q >> 2) + 4 * half + (q & 3);
+        const int col = wj * 32 + r32;
+        dst[row * kGramBlock + col] = make_double2(dr[q], di[q]);
+    }
+}
+
+// Sum the chunk partials in FP64 and write the full Hermitian C[plane][F][F].
+__global__ void gram_reduce_kernel(const double2 *__restrict__ part, double2 *__restrict__ C,
+                                   int F, int pairs, int chunks, int nblk, int planes)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)planes * F * F) return;
+    const int plane = (int)(idx / ((size_t)F * F));
+    const int f1 = (int)((idx / F) % F), f2 = (int)(idx % F);
+    int a = f1, b = f2;
+    const bool swap = (f1 / kGramBlock) > (f2 / kGramBlock);
+    if (swap) { a = f2; b = f1; }
+    const int I = a / kGramBlock, J = b / kGramBlock;
+    int pair = 0;
+    for (int i = 0; i < I; ++i) pair += nblk - i;
+    pair += J - I;
+    const double2 *src = part + (size_t)(plane * pairs + pair) * chunks * kGramBlock * kGramBlock +
+                         (a % kGramBlock) * kGramBlock + (b % kGramBlock);
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        const double2 v = src[(size_t)c * kGramBlock * kGramBlock];
+        re += v.x;
+        im += v.y;
+    }
+    C[idx] = make_double2(re, swap ? -im : im);
+}
+
+// ---------------------------------------------------------------- eigensolver
+constexpr int kEigThreads = 512;
+constexpr int kEigWaves = kEigThreads / 64;
+constexpr int kMaxF = 1024;
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < kEigWaves; ++i) s += red[i];
+    return s;
+}
+
+__device__ inline double block_max(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < kEigWaves; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconjmul(double2 a, double2 b) {   // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x.
+__device__ inline int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
+    double q = d[0] - x;
+    int cnt = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        if (fabs(q) <= pivmin) q = -pivmin;
+        q = d[i] - x - e2[i - 1] / q;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// One work-group per plane.  Workspace per plane: C (tridiagonalised in place,
+// Householder vectors in the rows), tau, d, e, eigenvalues, and scratch for
+// the c tridiagonal eigenvectors (real) and their complex back-transforms.
+__global__ __launch_bounds__(kEigThreads) void eigen_kernel(
+    double2 *__restrict__ Cbuf, double2 *__restrict__ taubuf, double *__restrict__ dbuf,
+    double *__restrict__ ebuf, double *__restrict__ evals, double2 *__restrict__ evecs,
+    double *__restrict__ tscratch, double2 *__restrict__ xscratch, int F, int c,
+    int *__restrict__ status, double *__restrict__ evals_out)
+{
+    const int plane = blockIdx.x;
+    const int t = threadIdx.x;
+    double2 *A = Cbuf + (size_t)plane * F * F;
+    double2 *tau = taubuf + (size_t)plane * F;
+    double *d = dbuf + (size_t)plane * F;
+    double *e = ebuf + (size_t)plane * F;
+    double *lam = evals + (size_t)plane * F;
+    double2 *V = evecs + (size_t)plane * F * (c > 0 ? c : 1);
+
+    __shared__ double2 sv[kMaxF];
+    __shared__ double2 sw[kMaxF];
+    __shared__ double2 part[kEigThreads];
+    __shared__ double red[kEigWaves];
+    __shared__ double sd[kMaxF];
+    __shared__ double se2[kMaxF];
+
+    // non-finite covariance: leave the plane unfiltered
+    double bad = 0.0;
+    for (size_t i = t; i < (size_t)F * F; i += kEigThreads) {
+        const double2 v = A[i];
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1.0;
+    }
+    bad = block_max(bad, red);
+    if (bad > 0.0) {
+        for (int i = t; i < F * c; i += kEigThreads) V[i] = make_double2(0.0, 0.0);
+        for (int i = t; i < F; i += kEigThreads) {
+            lam[i] = __builtin_nan("");
+            if (evals_out) evals_out[(size_t)plane * F + i] = lam[i];
+        }
+        if (t == 0) atomicOr(status, kStatusNumeric);
+        return;
+    }
+
+    // 1. Householder reduction to real tridiagonal form, T = Q^H C Q.
+    for (int k = 0; k + 1 < F; ++k) {
+        const int m = F - k - 1;
+        double2 *row = A + (size_t)k * F + k + 1;          // conj of the column below the diagonal
+        double nrm = 0.0;
+        for (int i = t; i < m; i += kEigThreads) {
+            const double2 x = make_double2(row[i].x, -row[i].y);
+            sv[i] = x;
+            if (i > 0) nrm += x.x * x.x + x.y * x.y;
+        }
+        nrm = block_sum(nrm, red);
+        const double2 alpha = sv[0];
+        double2 tk = make_double2(0.0, 0.0);
+        double beta = alpha.x;
+        if (nrm > 0.0 || alpha.y != 0.0) {
+            beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + nrm), alpha.x);
+            tk = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            // scale = 1 / (alpha - beta)
+            const double2 den = make_double2(alpha.x - beta, alpha.y);
+            const double dd = den.x * den.x + den.y * den.y;
+            const double2 scale = make_double2(den.x / dd, -den.y / dd);
+            __syncthreads();
+            for (int i = t; i < m; i += kEigThreads) sv[i] = i == 0 ? make_double2(1.0, 0.0) : cmul(sv[i], scale);
+        } else {
+            __syncthreads();
+            for (int i = t; i < m; i += kEigThreads) sv[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        for (int i = t; i < m; i += kEigThreads) row[i] = sv[i];
+        if (t == 0) {
+            d[k] = A[(size_t)k * F + k].x;
+            e[k] = beta;
+            tau[k] = tk;
+        }
+        if (tk.x == 0.0 && tk.y == 0.0) { __syncthreads(); continue; }
+
+        // p = tau * A22 v, using A22[i][j] = conj(A22[j][i]) for coalesced rows
+        double2 *A22 = A + (size_t)(k + 1) * F + (k + 1);
+        const int mp = (m + 63) & ~63;
+        if (mp <= kEigThreads) {
+            const int G = kEigThreads / mp;
+            const int i = t % mp, gi = t / mp;
+            double2 acc = make_double2(0.0, 0.0);
+            if (i < m && gi < G)
+                for (int j = gi; j < m; j += G) {
+                    const double2 a = A22[(size_t)j * F + i];
+                    const double2 v = sv[j];
+                    acc.x += a.x * v.x + a.y * v.y;
+                    acc.y += a.x * v.y - a.y * v.x;
+                }
+            part[t] = acc;
+            __syncthreads();
+            if (t < m) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int q = 0; q < G; ++q) { s.x += part[q * mp + t].x; s.y += part[q * mp + t].y; }
+                sw[t] = cmul(tk, s);
+            }
+        } else {
+            for (int i = t; i < m; i += kEigThreads) {
+                double2 acc = make_double2(0.0, 0.0);
+                for (int j = 0; j < m; ++j) {
+                    const double2 a = A22[(size_t)j * F + i];
+                    const double2 v = sv[j];
+                    acc.x += a.x * v.x + a.y * v.y;
+                    acc.y += a.x * v.y - a.y * v.x;
+                }
+                sw[i] = cmul(tk, acc);
+            }
+        }
+        __syncthreads();
+        // alpha2 = -1/2 tau (p^H v);  w = p + alpha2 v
+        double pr = 0.0, pi = 0.0;
+        for (int i = t; i < m; i += kEigThreads) {
+            const double2 q = cconjmul(sw[i], sv[i]);
+            pr += q.x;
+            pi += q.y;
+        }
+        pr = block_sum(pr, red);
+        pi = block_sum(pi, red);
+        const double2 a2 = cmul(make_double2(-0.5 * tk.x, -0.5 * tk.y), make_double2(pr, pi));
+        for (int i = t; i < m; i += kEigThreads) {
+            const double2 av = cmul(a2, sv[i]);
+            sw[i] = make_double2(sw[i].x + av.x, sw[i].y + av.y);
+        }
+        __syncthreads();
+        // A22 -= v w^H + w v^H
+        if (mp <= kEigThreads) {
+            const int G = kEigThreads / mp;
+            const int j = t % mp, gi = t / mp;
+            if (j < m && gi < G) {
+                const double2 vj = sv[j], wj = sw[j];
+                for (int i = gi; i < m; i += G) {
+                    const double2 vi = sv[i], wi = sw[i];
+                    double2 *a = A22 + (size_t)i * F + j;
+                    const double2 x = *a;
+                    // v_i conj(w_j) + w_i conj(v_j)
+                    const double re = vi.x * wj.x + vi.y * wj.y + wi.x * vj.x + wi.y * vj.y;
+                    const double im = vi.y * wj.x - vi.x * wj.y + wi.y * vj.x - wi.x * vj.y;
+                    *a = make_double2(x.x - re, x.y - im);
+                }
+            }
+        } else {
+            for (int i = 0; i < m; ++i)
+                for (int j = t; j < m; j += kEigThreads) {
+                    const double2 vi = sv[i], wi = sw[i], vj = sv[j], wj = sw[j];
+                    double2 *a = A22 + (size_t)i * F + j;
+                    const double2 x = *a;
+                    const double re = vi.x * wj.x + vi.y * wj.y + wi.x * vj.x + wi.y * vj.y;
+                    const double im = vi.y * wj.x - vi.x * wj.y + wi.y * vj.x - wi.x * vj.y;
+                    *a = make_double2(x.x - re, x.y - im);
+                }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        d[F - 1] = A[(size_t)(F - 1) * F + (F - 1)].x;
+        e[F - 1] = 0.0;
+        if (F >= 1) tau[F - 1] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    // 2. All eigenvalues by bisection on Sturm counts (descending order).
+    double lo_b = 1e300, hi_b = -1e300, emax = 0.0;
+    for (int i = t; i < F; i += kEigThreads) {
+        const double di = d[i];
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < F ? fabs(e[i]) : 0.0);
+        lo_b = fmin(lo_b, di - r);
+        hi_b = fmax(hi_b, di + r);
+        sd[i] = di;
+        se2[i] = (i + 1 < F) ? e[i] * e[i] : 0.0;
+        emax = fmax(emax, se2[i]);
+    }
+    hi_b = block_max(hi_b, red);
+    lo_b = -block_max(-lo_b, red);
+    emax = block_max(emax, red);
+    const double tnorm = fmax(fabs(lo_b), fabs(hi_b));
+    const double pivmin = fmax(DBL_MIN, DBL_MIN * emax);
+    lo_b -= 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+    hi_b += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+    for (int idx = t; idx < F; idx += kEigThreads) {
+        const int target = F - 1 - idx;
+        double lo = lo_b, hi = hi_b;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (sturm_count(sd, se2, F, mid, pivmin) > target) hi = mid; else lo = mid;
+        }
+        lam[idx] = 0.5 * (lo + hi);
+        if (evals_out) evals_out[(size_t)plane * F + idx] = lam[idx];
+    }
+    __syncthreads();
+    if (c <= 0) return;
+
+    // 3. Inverse iteration on T - lambda I for the c largest eigenvalues.
+    //    Partial-pivoting LU of the tridiagonal; one thread per eigenvector.
+    // scratch per vector: u0, u1, u2 (the three diagonals of U), ml (multipliers),
+    // b (right-hand side, then the solution), sw (1 where rows were swapped)
+    double *ts = tscratch + (size_t)plane * c * 6 * F;
+    if (t < c) {
+        double *u0 = ts + (size_t)t * 6 * F;
+        double *u1 = u0 + F, *u2 = u1 + F, *ml = u2 + F, *b = ml + F, *sw_ = b + F;
+        const double lm = lam[t];
+        const double tiny = DBL_EPSILON * tnorm + pivmin;
+        for (int i = 0; i < F; ++i) {
+            u0[i] = sd[i] - lm;
+            u1[i] = (i + 1 < F) ? e[i] : 0.0;
+            u2[i] = 0.0;
+            sw_[i] = 0.0;
+        }
+        for (int i = 0; i + 1 < F; ++i) {
+            const double sub = e[i];
+            if (fabs(u0[i]) >= fabs(sub)) {
+                if (u0[i] == 0.0) u0[i] = tiny;
+                ml[i] = sub / u0[i];
+                u0[i + 1] -= ml[i] * u1[i];
+            } else {
+                // swap rows i and i+1, then eliminate
+                const double l = u0[i] / sub;
+                const double t1 = u0[i + 1];
+                const double t2 = (i + 2 < F) ? u1[i + 1] : 0.0;
+                u0[i] = sub;
+                u0[i + 1] = u1[i] - l * t1;
+                if (i + 2 < F) u1[i + 1] = -l * t2;
+                u1[i] = t1;
+                u2[i] = t2;
+                ml[i] = l;
+                sw_[i] = 1.0;
+            }
+        }
+        if (u0[F - 1] == 0.0) u0[F - 1] = tiny;
+        // deterministic start vector
+        for (int i = 0; i < F; ++i) b[i] = 1.0 + 0.37 * sin(0.731 * i + 1.3 * t);
+        for (int it = 0; it < 3; ++it) {
+            for (int i = 0; i + 1 < F; ++i) {
+                if (sw_[i] != 0.0) { const double tmp = b[i]; b[i] = b[i + 1]; b[i + 1] = tmp; }
+                b[i + 1] -= ml[i] * b[i];
+            }
+            b[F - 1] /= u0[F - 1];
+            if (F >= 2) b[F - 2] = (b[F - 2] - u1[F - 2] * b[F - 1]) / u0[F - 2];
+            for (int i = F - 3; i >= 0; --i) b[i] = (b[i] - u1[i] * b[i + 1] - u2[i] * b[i + 2]) / u0[i];
+            double nrm2 = 0.0;
+            for (int i = 0; i < F; ++i) nrm2 += b[i] * b[i];
+            const double inv = 1.0 / sqrt(nrm2);
+            for (int i = 0; i < F; ++i) b[i] *= inv;
+        }
+    }
+    __syncthreads();
+
+    // 4. Orthonormalise the c tridiagonal eigenvectors (classical Gram-Schmidt,
+    //    two passes), one vector at a time against the earlier ones.
+    for (int i = 0; i < c; ++i) {
+        double *bi = ts + (size_t)i * 6 * F + 4 * F;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j = 0; j < i; ++j) {
+                const double *bj = ts + (size_t)j * 6 * F + 4 * F;
+                double dot = 0.0;
+                for (int q = t; q < F; q += kEigThreads) dot += bj[q] * bi[q];
+                dot = block_sum(dot, red);
+                for (int q = t; q < F; q += kEigThreads) bi[q] -= dot * bj[q];
+                __syncthreads();
+            }
+        }
+        double nrm2 = 0.0;
+        for (int q = t; q < F; q += kEigThreads) nrm2 += bi[q] * bi[q];
+        nrm2 = block_sum(nrm2, red);
+        const double inv = 1.0 / sqrt(nrm2);
+        for (int q = t; q < F; q += kEigThreads) bi[q] *= inv;
+        __syncthreads();
+    }
+
+    // 5. Back-transform x = H_0 H_1 ... H_{F-2} y; one wave per vector.
+    double2 *xs = xscratch + (size_t)plane * c * F;
+    for (int i = t; i < c * F; i += kEigThreads) {
+        const int vi = i / F, q = i % F;
+        xs[i] = make_double2(ts[(size_t)vi * 6 * F + 4 * F + q], 0.0);
+    }
+    __syncthreads();
+    const int lane = t & 63, wave = t >> 6;
+    for (int vi = wave; vi < c; vi += kEigWaves) {
+        double2 *x = xs + (size_t)vi * F;
+        for (int k = F - 2; k >= 0; --k) {
+            const double2 tk = tau[k];
+            if (tk.x == 0.0 && tk.y == 0.0) continue;
+            const int m = F - k - 1;
+            const double2 *v = A + (size_t)k * F + k + 1;
+            double sr = 0.0, si = 0.0;
+            for (int q = lane; q < m; q += 64) {
+                const double2 p = cconjmul(v[q], x[k + 1 + q]);
+                sr += p.x;
+                si += p.y;
+            }
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            const double2 s = cmul(tk, make_double2(sr, si));
+            for (int q = lane; q < m; q += 64) {
+                const double2 p = cmul(v[q], s);
+                x[k + 1 + q] = make_double2(x[k + 1 + q].x - p.x, x[k + 1 + q].y - p.y);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < c * F; i += kEigThreads) {
+        const int vi = i % c, f = i / c;
+        V[(size_t)f * c + vi] = xs[(size_t)vi * F + f];
+    }
+}
+
+__global__ void clear_status_kernel(int *status) {
+    if (threadIdx.x == 0) *status = 0;
+}
+
+// ---------------------------------------------------------------- removal
+// I_f = I - (I V_c) V_c^H per pixel time series, accumulated in FP64.
+template <int CM>
+__global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
+                                                      const double2 *__restrict__ V, int F,
+                                                      int npix, int c)
+{
+    const int plane = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    float2 *col = P + (size_t)plane * F * npix + p;
+    const double2 *Vp = V + (size_t)plane * F * c;
+    double2 y[CM];
+#pragma unroll
+    for (int i = 0; i < CM; ++i) y[i] = make_double2(0.0, 0.0);
+    for (int g = 0; g < F; ++g) {
+        const float2 xf = col[(size_t)g * npix];
+        const double xr = xf.x, xi = xf.y;
+#pragma unroll
+        for (int i = 0; i < CM; ++i) {
+            if (i < c) {
+                const double2 v = Vp[g * c + i];
+                y[i].x = fma(xr, v.x, fma(-xi, v.y, y[i].x));
+                y[i].y = fma(xr, v.y, fma(xi, v.x, y[i].y));
+            }
+        }
+    }
+    for (int f = 0; f < F; ++f) {
+        const float2 xf = col[(size_t)f * npix];
+        double rr = 0.0, ri = 0.0;
+#pragma unroll
+        for (int i = 0; i < CM; ++i) {
+            if (i < c) {
+                const double2 v = Vp[f * c + i];   // y * conj(v)
+                rr = fma(y[i].x, v.x, fma(y[i].y, v.y, rr));
+                ri = fma(y[i].y, v.x, fma(-y[i].x, v.y, ri));
+            }
+        }
+        col[(size_t)f * npix] = make_float2((float)((double)xf.x - rr), (float)((double)xf.y - ri));
+    }
+}
+
+hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, char *ws,
+                         hipStream_t st)
+{
+    const Geometry &g = ctx->geo;
+    const Workspace &w = ctx->ws;
+    const int F = g.n_frames, npix = g.nz * g.nu, planes = g.n_planes;
+    const int c = ctx->cfg.svd_cutoff;
+    const int nblk = cdiv(F, kGramBlock);
+    double2 *part = (double2 *)(ws + w.gram_part);
+    double2 *C = (double2 *)(ws + w.cov);
+    int *status = (int *)(ws + w.status);
+
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, st, status);
+    const int nwg = planes * w.gram_pairs * w.gram_chunks;
+    if (ctx->cfg.precision == ULM_PREC_BF16X3)
+        hipLaunchKernelGGL(gram_bf16x3_kernel, dim3(nwg), dim3(256), 0, st, proj, part, F, npix,
+                           w.gram_pairs, w.gram_chunks, nblk);
+    else
+        hipLaunchKernelGGL(gram_f64_kernel, dim3(nwg), dim3(256), 0, st, proj, part, F, npix,
+                           w.gram_pairs, w.gram_chunks, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t nC = (size_t)planes * F * F;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)cdiv<size_t>(nC, 256)), dim3(256), 0, st,
+                       part, C, F, w.gram_pairs, w.gram_chunks, nblk, planes);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    double *evals = (double *)(ws + w.evals);
+    hipLaunchKernelGGL(eigen_kernel, dim3(planes), dim3(kEigThreads), 0, st, C,
+                       (double2 *)(ws + w.tau), (double *)(ws + w.diag), (double *)(ws + w.offd),
+                       evals, (double2 *)(ws + w.evecs), (double *)(ws + w.tscratch),
+                       (double2 *)(ws + w.xscratch), F, c, status, eigvals_out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (c > 0) {
+        dim3 grid(cdiv(npix, 256), planes);
+        const double2 *V = (const double2 *)(ws + w.evecs);
+        if (c <= 4)
+            hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+        else if (c <= 8)
+            hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+        else if (c <= 16)
+            hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+        else if (c <= 24)
+            hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+        else
+            hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ulm

@@ -1,0 +1,123 @@
+"""The C ABI: library loads, exports every declared symbol, the ctypes mirror of
+the structs matches the C layout, and invalid configurations are rejected on
+the host (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ulmproj.h")
+
+
+def _lib():
+    from paper_2511_21647_amd import _lib as L
+    return L
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:const\s+char\s*\*|int32_t)\s*(\w+)\s*\(", text, re.M))
+    assert declared == set(L.EXPORTS)
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for name in declared:
+        assert hasattr(raw, name), name
+
+
+def test_struct_layout_matches_header(tmp_path):
+    L = _lib()
+    src = tmp_path / "layout.c"
+    fields = [f[0] for f in L.ULMConfig._fields_]
+    body = "\n".join(f'printf("%s %zu\\n", "{f}", offsetof(ulm_config_t, {f}));' for f in fields)
+    loc_fields = list(L.LOC_DTYPE.names)
+    body += "\n" + "\n".join(f'printf("loc.%s %zu\\n", "{f}", offsetof(ulm_loc_t, {f}));'
+                             for f in loc_fields)
+    src.write_text(f"""#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+{body}
+printf("sizeof_config %zu\\n", sizeof(ulm_config_t));
+printf("sizeof_loc %zu\\n", sizeof(ulm_loc_t));
+printf("sizeof_timing %zu\\n", sizeof(ulm_timing_t));
+return 0; }}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(L.ULMConfig, f).offset, f
+    for f in loc_fields:
+        assert int(out["loc." + f]) == L.LOC_DTYPE.fields[f][1], f
+    assert int(out["sizeof_config"]) == ctypes.sizeof(L.ULMConfig)
+    assert int(out["sizeof_loc"]) == L.LOC_DTYPE.itemsize
+    assert int(out["sizeof_timing"]) == ctypes.sizeof(L.ULMTiming)
+
+
+def _create(cfg_struct):
+    L = _lib()
+    h = ctypes.c_void_p()
+    rc = L._lib.ulm_create(ctypes.byref(cfg_struct), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda c: setattr(c, "n_angles", 0), "n_angles"),
+    (lambda c: setattr(c, "n_angles", 33), "n_angles"),
+    (lambda c: setattr(c, "ncc_size", 8), "ncc_size"),
+    (lambda c: setattr(c, "ncc_size", 17), "ncc_size"),
+    (lambda c: setattr(c, "svd_cutoff", 33), "svd_cutoff"),
+    (lambda c: setattr(c, "svd_cutoff", -1), "svd_cutoff"),
+    (lambda c: setattr(c, "n_frames", 2000), "n_frames"),
+    (lambda c: setattr(c, "pitch", 0.0), "physical"),
+    (lambda c: setattr(c, "precision", 7), "precision"),
+    (lambda c: setattr(c, "n_blocks", 0), "grid"),
+    (lambda c: setattr(c, "nu", 4000), "NCC band"),
+    (lambda c: setattr(c, "z0", -1e-3), "z0"),
+])
+def test_invalid_config_rejected_on_host(mutate, msg):
+    from synth import cfg_paper
+    L = _lib()
+    c = L.make_config(cfg_paper())
+    mutate(c)
+    rc, h = _create(c)
+    assert rc == L.ULM_ERR_INVALID_ARG
+    assert msg in L.last_error()
+    assert not h.value
+
+
+def test_delay_span_too_large_rejected():
+    """A grid whose tile delay span exceeds the staged sample window is refused."""
+    from synth import cfg_paper
+    L = _lib()
+    c = L.make_config(cfg_paper())
+    c.dz = 2e-3                     # 8 rows x 2 mm = a 14 mm tile: far beyond the window
+    rc, _ = _create(c)
+    assert rc == L.ULM_ERR_INVALID_ARG and "window" in L.last_error()
+
+
+def test_null_arguments():
+    L = _lib()
+    assert L._lib.ulm_create(None, None) == L.ULM_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert L._lib.ulm_workspace_size(None, ctypes.byref(n)) == L.ULM_ERR_INVALID_ARG
+    assert L._lib.rca_beamform_proj(None, None, None, None, 0, None) == L.ULM_ERR_INVALID_ARG
+    assert L._lib.svd_clutter_filter(None, None, None, None, 0, None) == L.ULM_ERR_INVALID_ARG
+    assert L._lib.ncc_localize(None, None, None, 0, None, None, 0, None) == L.ULM_ERR_INVALID_ARG
+    assert L._lib.ulm_destroy(None) == L.ULM_OK
+
+
+def test_paper_geometry_fits_window():
+    """The paper-scale and tiny configurations pass validation up to the first HIP
+    call (which fails without a GPU, or succeeds with one)."""
+    from synth import cfg_paper, cfg_tiny
+    L = _lib()
+    for cfg in (cfg_paper(), cfg_tiny()):
+        rc, h = _create(L.make_config(cfg))
+        assert rc in (L.ULM_OK, L.ULM_ERR_HIP), L.last_error()
+        if rc == L.ULM_OK:
+            L._lib.ulm_destroy(h)

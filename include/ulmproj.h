@@ -10,8 +10,9 @@
  *     last index fastest.
  *   - Device buffers are owned by the caller (allocated on the device that was
  *     current at ulm_create).  The context owns only its small tables.
- *   - The workspace `ws` (ws_bytes >= ulm_workspace_size) is caller-owned
- *     device memory; its contents between calls are unspecified, except that
+ *   - The workspace `ws` (ws_bytes >= ulm_workspace_size, 256-byte aligned)
+ *     is caller-owned device memory.  Zero-fill it once after allocating it;
+ *     its contents between calls are otherwise unspecified, except that
  *     ulm_check_status reads the status word the last call left there.
  *   - Calls are asynchronous on `stream` (NULL = the default stream); results
  *     are valid once the caller synchronises that stream.  No entry point

@@ -159,7 +159,7 @@ class Context:
         n = ctypes.c_size_t()
         _check(_lib.ulm_workspace_size(h, ctypes.byref(n)))
         self.ws_bytes = n.value
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws = torch.zeros(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
         self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
 

@@ -129,6 +129,13 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.evecs = take(sizeof(double2) * planes * F * cc);
     w.tscratch = take(sizeof(double) * planes * cc * 6 * F);
     w.xscratch = take(sizeof(double2) * planes * cc * F);
+    w.hvec = take(sizeof(double2) * planes * F * F);
+    w.vbuf = take(sizeof(double2) * planes * 2 * F);
+    w.pbuf = take(sizeof(double2) * planes * 2 * F);
+    w.dots = take(sizeof(double) * planes * 2 * 64);
+    w.scal = take(sizeof(double) * planes * 4);
+    w.bar = take(sizeof(int) * planes);
+    w.eflag = take(sizeof(int) * planes);
     w.fmax = take(sizeof(float) * planes * F);
     w.band_cnt = take(sizeof(int) * planes * F * w.bands);
     w.band_off = take(sizeof(int) * planes * F * w.bands);

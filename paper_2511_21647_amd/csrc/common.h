@@ -56,6 +56,12 @@ struct Workspace {
     size_t evecs;       // [planes][F][c] c128
     size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
+    size_t hvec;        // [planes][F][F] c128      Householder vectors
+    size_t vbuf, pbuf;  // [planes][F] c128         reflector / A v exchange
+    size_t dots;        // [planes][32][2] f64
+    size_t scal;        // [planes][4] f64
+    size_t bar;         // [planes] i32             grid-barrier counters
+    size_t eflag;       // [planes] i32
     size_t fmax;        // [planes][F] f32
     size_t band_cnt;    // [planes][F][bands] i32
     size_t band_off;    // [planes][F][bands] i32

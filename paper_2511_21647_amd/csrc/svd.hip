@@ -15,6 +15,29 @@
 
 namespace ulm {
 
+struct EigArgs {
+    const double2 *C;
+    double2 *H;
+    double2 *tau;
+    double *d, *e;
+    double *lam;
+    double *lam_out;
+    double2 *V;
+    double *tscr;
+    double2 *xscr;
+    double2 *vbuf;
+    double2 *pbuf;
+    double *dots;
+    double *scal;
+    int *bar;
+    int *flag;
+    int *status;
+    int F, c, W, planes;
+};
+int eigen_coop_width(int F);
+size_t eigen_coop_lds(int F);
+hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st);
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -108,7 +131,8 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
         for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = wi * 32 + ti * 16 + 4 * kk + r;
+                // v_mfma_f64_16x16x4f64 result: lane l, register r holds D[4 r + l / 16][l % 16]
+                const int row = wi * 32 + ti * 16 + 4 * r + kk;
                 const int col = wj * 32 + tj * 16 + r16;
                 dst[row * kGramBlock + col] = make_double2(accr[ti][tj][r], acci[ti][tj][r]);
             }
@@ -279,7 +303,7 @@ __global__ __launch_bounds__(kEigThreads) void eigen_kernel(
     double2 *__restrict__ Cbuf, double2 *__restrict__ taubuf, double *__restrict__ dbuf,
     double *__restrict__ ebuf, double *__restrict__ evals, double2 *__restrict__ evecs,
     double *__restrict__ tscratch, double2 *__restrict__ xscratch, int F, int c,
-    int *__restrict__ status, double *__restrict__ evals_out)
+    int *__restrict__ status, double *__restrict__ evals_out, int *__restrict__ eflag)
 {
     const int plane = blockIdx.x;
     const int t = threadIdx.x;
@@ -310,7 +334,10 @@ __global__ __launch_bounds__(kEigThreads) void eigen_kernel(
             lam[i] = __builtin_nan("");
             if (evals_out) evals_out[(size_t)plane * F + i] = lam[i];
         }
-        if (t == 0) atomicOr(status, kStatusNumeric);
+        if (t == 0) {
+            atomicOr(status, kStatusNumeric);
+            atomicOr(eflag + plane, 1);
+        }
         return;
     }
 
@@ -581,8 +608,12 @@ __global__ __launch_bounds__(kEigThreads) void eigen_kernel(
     }
 }
 
-__global__ void clear_status_kernel(int *status) {
+__global__ void clear_status_kernel(int *status, int *bar, int *eflag, int planes) {
     if (threadIdx.x == 0) *status = 0;
+    for (int i = threadIdx.x; i < planes; i += blockDim.x) {
+        bar[i] = 0;
+        eflag[i] = 0;
+    }
 }
 
 // ---------------------------------------------------------------- removal
@@ -590,9 +621,10 @@ __global__ void clear_status_kernel(int *status) {
 template <int CM>
 __global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
                                                       const double2 *__restrict__ V, int F,
-                                                      int npix, int c)
+                                                      int npix, int c, const int *__restrict__ eflag)
 {
     const int plane = blockIdx.y;
+    if (eflag[plane]) return;      // non-finite covariance: the plane stays unfiltered
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     float2 *col = P + (size_t)plane * F * npix + p;
@@ -639,7 +671,8 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
     double2 *C = (double2 *)(ws + w.cov);
     int *status = (int *)(ws + w.status);
 
-    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, st, status);
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, st, status, (int *)(ws + w.bar),
+                       (int *)(ws + w.eflag), planes);
     const int nwg = planes * w.gram_pairs * w.gram_chunks;
     if (ctx->cfg.precision == ULM_PREC_BF16X3)
         hipLaunchKernelGGL(gram_bf16x3_kernel, dim3(nwg), dim3(256), 0, st, proj, part, F, npix,
@@ -655,24 +688,51 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     double *evals = (double *)(ws + w.evals);
-    hipLaunchKernelGGL(eigen_kernel, dim3(planes), dim3(kEigThreads), 0, st, C,
-                       (double2 *)(ws + w.tau), (double *)(ws + w.diag), (double *)(ws + w.offd),
-                       evals, (double2 *)(ws + w.evecs), (double *)(ws + w.tscratch),
-                       (double2 *)(ws + w.xscratch), F, c, status, eigvals_out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (eigen_coop_lds(F) <= 150 * 1024) {
+        EigArgs a;
+        a.C = C;
+        a.H = (double2 *)(ws + w.hvec);
+        a.tau = (double2 *)(ws + w.tau);
+        a.d = (double *)(ws + w.diag);
+        a.e = (double *)(ws + w.offd);
+        a.lam = evals;
+        a.lam_out = eigvals_out;
+        a.V = (double2 *)(ws + w.evecs);
+        a.tscr = (double *)(ws + w.tscratch);
+        a.xscr = (double2 *)(ws + w.xscratch);
+        a.vbuf = (double2 *)(ws + w.vbuf);
+        a.pbuf = (double2 *)(ws + w.pbuf);
+        a.dots = (double *)(ws + w.dots);
+        a.scal = (double *)(ws + w.scal);
+        a.bar = (int *)(ws + w.bar);
+        a.flag = (int *)(ws + w.eflag);
+        a.status = status;
+        a.F = F;
+        a.c = c;
+        a.W = eigen_coop_width(F);
+        a.planes = planes;
+        if ((e = launch_eigen_coop(a, st)) != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(eigen_kernel, dim3(planes), dim3(kEigThreads), 0, st, C,
+                           (double2 *)(ws + w.tau), (double *)(ws + w.diag), (double *)(ws + w.offd),
+                           evals, (double2 *)(ws + w.evecs), (double *)(ws + w.tscratch),
+                           (double2 *)(ws + w.xscratch), F, c, status, eigvals_out, (int *)(ws + w.eflag));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (c > 0) {
         dim3 grid(cdiv(npix, 256), planes);
         const double2 *V = (const double2 *)(ws + w.evecs);
+        const int *eflag = (const int *)(ws + w.eflag);
         if (c <= 4)
-            hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+            hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
         else if (c <= 8)
-            hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+            hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
         else if (c <= 16)
-            hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+            hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
         else if (c <= 24)
-            hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+            hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
         else
-            hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, V, F, npix, c);
+            hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -4,6 +4,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -48,34 +49,10 @@ static int32_t hip_fail(hipError_t e, const char *where) {
 
 extern "C" const char *ulm_last_error(void) { return g_err.c_str(); }
 
-// Sample window of the stage-1 beamformer: every pixel of a tile must find
-// floor(s) and floor(s) + 1 inside the kDasLen samples staged from
-// floor(s_min) - 1, where s_min is taken at the tile's shallowest row and the
-// column nearest to the element.  Checked in FP64 with a margin.
-static bool das_window_fits(const ulm_config_t &c, const std::vector<double> &stx, double *worst) {
-    const int n_tu = cdiv(c.nu, kDasTileU), n_tz = cdiv(c.nz, kDasTileZ);
-    double w = 0.0;
-    const double fs_c = c.fs / c.c;
-    for (int k = 0; k < c.n_angles; ++k)
-        for (int tz = 0; tz < n_tz; ++tz) {
-            const int l0 = tz * kDasTileZ, l1 = std::min(l0 + kDasTileZ, c.nz) - 1;
-            const double z0 = c.z0 + l0 * c.dz, z1 = c.z0 + l1 * c.dz;
-            for (int tu = 0; tu < n_tu; ++tu) {
-                const int i0 = tu * kDasTileU, i1 = std::min(i0 + kDasTileU, c.nu) - 1;
-                const double ua = c.u0 + i0 * c.du, ub = c.u0 + i1 * c.du;
-                for (int j = 0; j < c.n_elem; ++j) {
-                    const double ej = (j - 0.5 * (c.n_elem - 1)) * c.pitch;
-                    const double un = std::min(std::max(ej, ua), ub);
-                    const double uf = fabs(ua - ej) > fabs(ub - ej) ? ua : ub;
-                    const double smin = hypot(un - ej, z0) * fs_c + stx[k * c.nz + l0];
-                    const double smax = hypot(uf - ej, z1) * fs_c + stx[k * c.nz + l1];
-                    w = std::max(w, smax - smin);
-                }
-            }
-        }
-    *worst = w;
-    // staged: floor(smin) - 1 ... ; needed up to floor(smax) + 1, plus one sample of margin
-    return w + 4.0 <= (double)(kDasLen - 1);
+static void free_tables(ulm_ctx *ctx) {
+    Tables &t = ctx->tab;
+    void *ptrs[] = {t.stx, t.sti, t.phz, t.rxd, t.rxp, t.win, t.taps, t.tap_meta, t.angles};
+    for (void *p : ptrs) (void)hipFree(p);
 }
 
 static int32_t validate(const ulm_config_t &c) {
@@ -151,37 +128,84 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
     if (rc != ULM_OK) return rc;
     const ulm_config_t &c = *cfg;
 
-    // stage-1 transmit delay (in samples, relative to t_start) and per-depth phase
+    // stage-1 tables (FP64 on the host, rounded to FP32):
+    //   (tau_tx(v_ref, z) + z / c - t_start) fs = sti[k][z] + stx[k][z]  (integer + fraction),
+    //   phz[k][z] = exp(i 2 pi f0 (tau_tx - z / c))
+    //   rxd[e][pix] = (r - z) fs / c,  rxp[e][pix] = exp(i 2 pi f0 (r - z) / c),  r - z = dx^2 / (r + z)
     const double L = (c.n_elem - 1) * c.pitch;
-    std::vector<double> stx_d((size_t)c.n_angles * c.nz);
+    const size_t npix = (size_t)c.nz * c.nu;
     std::vector<float> stx((size_t)c.n_angles * c.nz);
+    std::vector<int> sti((size_t)c.n_angles * c.nz);
     std::vector<float2> phz((size_t)c.n_angles * c.nz);
     for (int k = 0; k < c.n_angles; ++k) {
         const double th = c.angles_rad[k];
         for (int l = 0; l < c.nz; ++l) {
             const double z = c.z0 + l * c.dz;
             const double ttx = (z * cos(th) + c.v_ref * sin(th) + 0.5 * L * fabs(sin(th))) / c.c;
-            stx_d[k * c.nz + l] = (ttx - c.t_start) * c.fs;
-            stx[k * c.nz + l] = (float)stx_d[k * c.nz + l];
+            const double sfull = (ttx + z / c.c - c.t_start) * c.fs;
+            const double sint = floor(sfull);
+            stx[k * c.nz + l] = (float)(sfull - sint);       // fraction in [0, 1)
+            sti[k * c.nz + l] = (int)sint;
             double cyc = c.f0 * (ttx - z / c.c);
             cyc -= nearbyint(cyc);
             phz[k * c.nz + l] = make_float2((float)cos(2 * M_PI * cyc), (float)sin(2 * M_PI * cyc));
         }
     }
-    double worst = 0;
-    if (!das_window_fits(c, stx_d, &worst)) {
+    std::vector<float> rxd((size_t)c.n_elem * npix);
+    std::vector<float2> rxp((size_t)c.n_elem * npix);
+    for (int e = 0; e < c.n_elem; ++e) {
+        const double ue = (e - 0.5 * (c.n_elem - 1)) * c.pitch;
+        for (int l = 0; l < c.nz; ++l) {
+            const double z = c.z0 + l * c.dz;
+            for (int i = 0; i < c.nu; ++i) {
+                const double dx = c.u0 + i * c.du - ue;
+                const double drz = dx * dx / (sqrt(dx * dx + z * z) + z);
+                const size_t q = (size_t)e * npix + (size_t)l * c.nu + i;
+                rxd[q] = (float)(drz * c.fs / c.c);
+                double cyc = c.f0 * drz / c.c;
+                cyc -= nearbyint(cyc);
+                rxp[q] = make_float2((float)cos(2 * M_PI * cyc), (float)sin(2 * M_PI * cyc));
+            }
+        }
+    }
+    // DAS windows: for every (transmit, tile, element) the first sample any pixel
+    // of the tile reads, from the same FP32 sum s = rxd + stx the kernel forms
+    const int n_tu = cdiv(c.nu, kDasTileU), n_tz = cdiv(c.nz, kDasTileZ), n_tiles = n_tu * n_tz;
+    std::vector<int> win((size_t)c.n_angles * n_tiles * c.n_elem);
+    int wspan = 0;
+    for (int k = 0; k < c.n_angles; ++k)
+        for (int tz = 0; tz < n_tz; ++tz)
+            for (int tu = 0; tu < n_tu; ++tu)
+                for (int e = 0; e < c.n_elem; ++e) {
+                    int lo = 1 << 30, hi = -(1 << 30);
+                    for (int l = tz * kDasTileZ; l < std::min((tz + 1) * kDasTileZ, c.nz); ++l) {
+                        const float sz = stx[k * c.nz + l];
+                        const int si = sti[k * c.nz + l];
+                        const float *rr = rxd.data() + (size_t)e * npix + (size_t)l * c.nu;
+                        for (int i = tu * kDasTileU; i < std::min((tu + 1) * kDasTileU, c.nu); ++i) {
+                            const volatile float sv = rr[i] + sz;     // IEEE single-precision sum
+                            const int fl = (int)floorf(sv) + si;
+                            lo = std::min(lo, fl);
+                            hi = std::max(hi, fl);
+                        }
+                    }
+                    win[((size_t)k * n_tiles + (tz * n_tu + tu)) * c.n_elem + e] = lo;
+                    wspan = std::max(wspan, hi - lo + 1);
+                }
+    const int das_len = wspan <= 64 ? 64 : (wspan <= 128 ? 128 : 0);
+    if (!das_len) {
         char buf[160];
-        snprintf(buf, sizeof buf, "delay span of a beamforming tile (%.1f samples) exceeds the %d-sample window",
-                 worst, kDasLen);
+        snprintf(buf, sizeof buf, "delay span of a beamforming tile (%d samples) exceeds the 128-sample window",
+                 wspan);
         return fail(ULM_ERR_INVALID_ARG, buf);
     }
 
     // stage-2 axial taps per (transmit, block): H[d] = sum_m exp(i phi_m) Lambda(d_m - d)
     const int per = cdiv(c.nv, c.n_blocks);
-    int dmin = 0, dmax = 0;
     std::vector<std::vector<std::complex<double>>> acc((size_t)c.n_angles * c.n_blocks);
-    std::vector<int> acc_lo((size_t)c.n_angles * c.n_blocks);
+    std::vector<int2> meta((size_t)c.n_angles * c.n_blocks);
     const int span = 4 * (c.nz + 8);
+    int max_taps = 1;
     for (int k = 0; k < c.n_angles; ++k) {
         const double tk = tan(0.5 * c.angles_rad[k]);
         for (int b = 0; b < c.n_blocks; ++b) {
@@ -199,20 +223,23 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
                 h[n + span] += (1.0 - fr) * e;
                 h[n + 1 + span] += fr * e;
             }
+            int lo = 0, hi = -1;
             for (int q = 0; q <= 2 * span; ++q)
                 if (h[q] != 0.0) {
-                    dmin = std::min(dmin, q - span);
-                    dmax = std::max(dmax, q - span);
+                    if (hi < lo) lo = q;
+                    hi = q;
                 }
+            if (hi < lo) lo = hi = span;        // an empty block: one zero tap
+            meta[k * c.n_blocks + b] = make_int2(lo - span, hi - lo + 1);
+            max_taps = std::max(max_taps, hi - lo + 1);
         }
     }
-    const int n_taps = dmax - dmin + 1;
-    if (n_taps > kFirMaxTaps) return fail(ULM_ERR_INVALID_ARG, "stage-2 shift needs too many taps");
-    std::vector<float2> taps((size_t)c.n_angles * c.n_blocks * n_taps);
+    if (max_taps > kFirMaxTaps) return fail(ULM_ERR_INVALID_ARG, "stage-2 shift needs too many taps");
+    std::vector<float2> taps((size_t)c.n_angles * c.n_blocks * max_taps, make_float2(0.f, 0.f));
     for (int kb = 0; kb < c.n_angles * c.n_blocks; ++kb)
-        for (int q = 0; q < n_taps; ++q) {
-            const std::complex<double> v = acc[kb][dmin + q + span];
-            taps[(size_t)kb * n_taps + q] = make_float2((float)v.real(), (float)v.imag());
+        for (int q = 0; q < meta[kb].y; ++q) {
+            const std::complex<double> v = acc[kb][meta[kb].x + q + span];
+            taps[(size_t)kb * max_taps + q] = make_float2((float)v.real(), (float)v.imag());
         }
 
     ulm_ctx *ctx = new (std::nothrow) ulm_ctx();
@@ -235,15 +262,12 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
     g.dz = (float)c.dz;
     g.u0 = (float)c.u0;
     g.z0 = (float)c.z0;
-    ctx->tab.tap_min = dmin;
-    ctx->tab.n_taps = n_taps;
+    ctx->tab.n_taps = max_taps;
     layout_workspace(ctx);
 
+    ctx->tab.das_len = das_len;
     auto cleanup = [&](hipError_t e, const char *where) {
-        (void)hipFree(ctx->tab.stx);
-        (void)hipFree(ctx->tab.phz);
-        (void)hipFree(ctx->tab.taps);
-        (void)hipFree(ctx->tab.angles);
+        free_tables(ctx);
         delete ctx;
         return hip_fail(e, where);
     };
@@ -252,7 +276,22 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
     if ((e = hipMalloc(&ctx->tab.stx, sizeof(float) * stx.size())) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->tab.phz, sizeof(float2) * phz.size())) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->tab.taps, sizeof(float2) * taps.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.tap_meta, sizeof(int2) * meta.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMemcpy(ctx->tab.tap_meta, meta.data(), sizeof(int2) * meta.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
     if ((e = hipMalloc(&ctx->tab.angles, sizeof(double) * ULM_MAX_ANGLES)) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.rxd, sizeof(float) * rxd.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.sti, sizeof(int) * sti.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMemcpy(ctx->tab.sti, sti.data(), sizeof(int) * sti.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMalloc(&ctx->tab.rxp, sizeof(float2) * rxp.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->tab.win, sizeof(int) * win.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMemcpy(ctx->tab.rxd, rxd.data(), sizeof(float) * rxd.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMemcpy(ctx->tab.rxp, rxp.data(), sizeof(float2) * rxp.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
+    if ((e = hipMemcpy(ctx->tab.win, win.data(), sizeof(int) * win.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(e, "hipMemcpy");
     if ((e = hipMemcpy(ctx->tab.stx, stx.data(), sizeof(float) * stx.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(e, "hipMemcpy");
     if ((e = hipMemcpy(ctx->tab.phz, phz.data(), sizeof(float2) * phz.size(), hipMemcpyHostToDevice)) != hipSuccess)
@@ -266,10 +305,7 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
         return cleanup(e, "hipDeviceGetAttribute");
     if (ncc_lds_bytes(c.nu, (c.ncc_size - 1) / 2) > (size_t)lds_max ||
         (size_t)2 * 8 * c.n_samp * sizeof(float) > (size_t)lds_max) {
-        (void)hipFree(ctx->tab.stx);
-        (void)hipFree(ctx->tab.phz);
-        (void)hipFree(ctx->tab.taps);
-        (void)hipFree(ctx->tab.angles);
+        free_tables(ctx);
         delete ctx;
         return fail(ULM_ERR_INVALID_ARG, "plane width or sample count exceeds the device's LDS per work-group");
     }
@@ -281,10 +317,7 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
 
 extern "C" int32_t ulm_destroy(ulm_ctx_t *ctx) {
     if (!ctx) return ULM_OK;
-    (void)hipFree(ctx->tab.stx);
-    (void)hipFree(ctx->tab.phz);
-    (void)hipFree(ctx->tab.taps);
-    (void)hipFree(ctx->tab.angles);
+    free_tables(ctx);
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ctx->ev[i]);
     delete ctx;
     return ULM_OK;

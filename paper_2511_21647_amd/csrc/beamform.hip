@@ -4,10 +4,11 @@
 // Stage 1 (das_stage1_kernel): per transmit, delay-and-sum of all receive
 // elements into the reference slice S_k(u, z).  One work-group owns an 8 x 32
 // pixel tile, one transmit and 16 frames: the delay, interpolation weight and
-// phasor of each (pixel, element) pair are evaluated once and applied to all 16
-// frames.  For each element the samples that the tile can reach are staged in
-// LDS (double-buffered, next element's global loads in flight during the
-// current element's arithmetic), so the gathers hit LDS, not the cache.
+// phasor of each (pixel, element) pair are read once and applied to all 16
+// frames.  For each element the samples that the tile can reach (at most 64 or
+// 128, exact window from the host) are staged in LDS, double-buffered: the
+// next element's global loads are in flight during the current element's
+// arithmetic, so the gathers hit LDS, not the cache.
 //
 // Stage 2 (stage2_fir_kernel): extrapolation along the transmit direction,
 // coherent compounding and slab projection collapse into one complex axial FIR
@@ -25,16 +26,30 @@ __device__ inline int xcd_remap(int lin, int n) {
     return x * q + min(x, r) + s;
 }
 
-template <int FB>
+// Stage-1 DAS.  The receive part of each (pixel, element) delay and phasor
+// comes from host-computed FP64 tables (rounded to FP32):
+//   rxd[e][pixel] = (r - z) fs / c,   rxp[e][pixel] = exp(i 2 pi f0 (r - z) / c),
+// r = sqrt((u - u_e)^2 + z^2); the per-(depth, transmit) part is
+//   (tau_tx + z / c - t_start) fs = sti[k][z] + stz[k][z] (integer + fraction),
+//   phz[k][z] = exp(i 2 pi f0 (tau_tx - z / c)).
+// The sample index is sti + (rxd + stz): the FP32 sum stays below a few hundred
+// samples, and the host forms the same sum to find each (transmit, tile,
+// element) window start win[...] exactly.
+// LDS holds, per staged sample, (IQ[s], IQ[s+1] - IQ[s]) so the interpolation
+// is two FMAs per frame.
+template <int FB, int LEN>
 __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
-    const float2 *__restrict__ iq, float2 *__restrict__ S, const float *__restrict__ stx,
-    const float2 *__restrict__ phz, Geometry g, int n_tu, int n_tz, int n_fb)
+    const float2 *__restrict__ iq, float2 *__restrict__ S, const float *__restrict__ stz,
+    const int *__restrict__ sti, const float2 *__restrict__ phz, const float *__restrict__ rxd,
+    const float2 *__restrict__ rxp, const int *__restrict__ win, Geometry g, int n_tu, int n_tz,
+    int n_fb)
 {
-    const int n_wg = n_tu * n_tz * n_fb * 2 * g.n_angles;
+    const int n_tiles = n_tu * n_tz;
+    const int n_wg = n_tiles * n_fb * 2 * g.n_angles;
     const int w = xcd_remap(blockIdx.x, n_wg);
-    const int tile = w % (n_tu * n_tz);
-    const int fb = (w / (n_tu * n_tz)) % n_fb;
-    const int ok = w / (n_tu * n_tz * n_fb);
+    const int tile = w % n_tiles;
+    const int fb = (w / n_tiles) % n_fb;
+    const int ok = w / (n_tiles * n_fb);
     const int o = ok / g.n_angles, k = ok % g.n_angles;
     const int tz = tile / n_tu, tu = tile % n_tu;
 
@@ -43,53 +58,63 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     const int iu = tu * kDasTileU + t % kDasTileU;
     const bool valid = iz < g.nz && iu < g.nu;
     const int izc = min(iz, g.nz - 1), iuc = min(iu, g.nu - 1);
-    const float z = g.z0 + izc * g.dz;
-    const float u = g.u0 + iuc * g.du;
-    const float stx_p = stx[k * g.nz + izc];
+    const int npix = g.nz * g.nu;
+    const int pix = izc * g.nu + iuc;
+    const float stz_p = stz[k * g.nz + izc];
+    const int sti_p = sti[k * g.nz + izc];
+    const int *wj = win + (size_t)(k * n_tiles + tile) * g.n_elem;
 
-    // Tile extent (clamped to the grid) for the per-element sample window.
-    const int iz_lo = tz * kDasTileZ, iu_lo = tu * kDasTileU;
-    const int iu_hi = min(iu_lo + kDasTileU, g.nu) - 1;
-    const float z_lo = g.z0 + iz_lo * g.dz;
-    const float u_lo = g.u0 + iu_lo * g.du, u_hi = g.u0 + iu_hi * g.du;
-    const float stx_lo = stx[k * g.nz + iz_lo];
-
-    __shared__ float2 buf[2][FB][kDasLen];
+    __shared__ float4 buf[2][FB][LEN];
 
     const size_t frame_stride = (size_t)2 * g.n_angles * g.n_elem * g.n_samp;
     const int f0 = fb * FB;
-    const float2 *blk = iq + ((size_t)f0 * 2 * g.n_angles + (size_t)o * g.n_angles + k) *
-                                 g.n_elem * g.n_samp;
-    const float half_ap = 0.5f * (g.n_elem - 1);
+    const float2 *blk = iq + ((size_t)o * g.n_angles + k) * g.n_elem * g.n_samp;
 
-    // First sample staged for element j: the smallest delay over the tile is at
-    // its shallowest row and the column nearest to the element.
-    auto window = [&](int j) -> int {
-        const float ej = (j - half_ap) * g.pitch;
-        const float dxn = fminf(fmaxf(ej, u_lo), u_hi) - ej;
-        const float r = sqrtf(fmaf(z_lo, z_lo, dxn * dxn));
-        return (int)floorf(fmaf(r, g.fs_over_c, stx_lo)) - 1;
-    };
-
-    constexpr int kPer = FB * kDasLen / kDasThreads;
-    float2 pre[kPer];
-    auto load = [&](int j, int s_lo) {
+    // staging map: each thread stages runs of 4 consecutive samples of one frame
+    // (5 loads give the 4 samples and their 4 forward differences)
+    constexpr int RUNS = LEN / 4;
+    constexpr int NQ = FB * RUNS / kDasThreads;
+    static_assert(NQ >= 1 && FB * RUNS % kDasThreads == 0, "staging map");
+    float4 st[NQ][4];
+    float prx;
+    float2 pph;
+    auto load = [&](int j) {
+        const int s_lo = wj[j];
+        const float2 *ch = blk + (size_t)j * g.n_samp;
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
-            const int f = e / kDasLen, s = e % kDasLen;
-            const int gs = s_lo + s;
-            float2 v = make_float2(0.f, 0.f);
-            if (f0 + f < g.n_frames && gs >= 0 && gs < g.n_samp)
-                v = blk[(size_t)f * frame_stride + (size_t)j * g.n_samp + gs];
-            pre[q] = v;
+            const int fl = e / RUNS, run = e % RUNS;
+            const int f = f0 + fl;
+            const float2 *row = ch + (size_t)min(f, g.n_frames - 1) * frame_stride;
+            const int gs = s_lo + 4 * run;
+            float2 x[5];
+            if (gs >= 0 && gs + 4 < g.n_samp) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) x[i] = row[gs + i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const int gi = gs + i;
+                    x[i] = (gi >= 0 && gi < g.n_samp) ? row[min(max(gi, 0), g.n_samp - 1)]
+                                                      : make_float2(0.f, 0.f);
+                }
+            }
+            // frames past the end read the last frame; their sums are never written
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                st[q][i] = make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
         }
+        prx = rxd[(size_t)j * npix + pix];
+        pph = rxp[(size_t)j * npix + pix];
     };
     auto store = [&](int b) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
-            buf[b][e / kDasLen][e % kDasLen] = pre[q];
+            const int fl = e / RUNS, run = e % RUNS;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) buf[b][fl][4 * run + i] = st[q][i];
         }
     };
 
@@ -97,64 +122,55 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
 #pragma unroll
     for (int f = 0; f < FB; ++f) acc[f] = make_float2(0.f, 0.f);
 
-    int s_lo = window(0);
-    load(0, s_lo);
+    load(0);
     store(0);
+    float crx = prx;
+    float2 cph = pph;
+    int s_lo = wj[0];
     __syncthreads();
 
     for (int j = 0; j < g.n_elem; ++j) {
         const int cur = j & 1;
-        int s_next = 0;
-        if (j + 1 < g.n_elem) {
-            s_next = window(j + 1);
-            load(j + 1, s_next);
-        }
-        // receive delay, fractional sample and phasor exp(i 2 pi f0 (r - z) / c)
-        const float ej = (j - half_ap) * g.pitch;
-        const float dx = u - ej;
-        const float dx2 = dx * dx;
-        const float r = sqrtf(fmaf(z, z, dx2));
-        const float s = fmaf(r, g.fs_over_c, stx_p);
+        const bool more = j + 1 < g.n_elem;
+        if (more) load(j + 1);
+        const float s = crx + stz_p;
         const float fl = floorf(s);
         const float fr = s - fl;
-        int idx = (int)fl - s_lo;
-        idx = min(max(idx, 0), kDasLen - 2);
-        float cyc = (dx2 / (r + z)) * g.f0_over_c;
-        cyc -= rintf(cyc);
-        float sn, cs;
-        sincospif(2.0f * cyc, &sn, &cs);
+        const int idx = min(max((int)fl + sti_p - s_lo, 0), LEN - 1);
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-            const float2 a = buf[cur][f][idx];
-            const float2 b = buf[cur][f][idx + 1];
-            const float xr = fmaf(fr, b.x - a.x, a.x);
-            const float xi = fmaf(fr, b.y - a.y, a.y);
-            acc[f].x = fmaf(cs, xr, fmaf(-sn, xi, acc[f].x));
-            acc[f].y = fmaf(cs, xi, fmaf(sn, xr, acc[f].y));
+            const float4 v = buf[cur][f][idx];
+            const float xr = fmaf(fr, v.z, v.x);
+            const float xi = fmaf(fr, v.w, v.y);
+            acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));
+            acc[f].y = fmaf(cph.x, xi, fmaf(cph.y, xr, acc[f].y));
         }
-        if (j + 1 < g.n_elem) store(cur ^ 1);
+        if (more) {
+            store(cur ^ 1);
+            crx = prx;
+            cph = pph;
+            s_lo = wj[j + 1];
+        }
         __syncthreads();
-        s_lo = s_next;
     }
 
     if (!valid) return;
     const float2 ph = phz[k * g.nz + izc];
-    const size_t plane = (size_t)g.nz * g.nu;
-    float2 *dst = S + ((size_t)(o * g.n_angles + k) * g.n_frames) * plane + (size_t)iz * g.nu + iu;
+    float2 *dst = S + ((size_t)(o * g.n_angles + k) * g.n_frames) * npix + (size_t)iz * g.nu + iu;
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
         if (f0 + f < g.n_frames) {
             float2 v;
             v.x = acc[f].x * ph.x - acc[f].y * ph.y;
             v.y = acc[f].x * ph.y + acc[f].y * ph.x;
-            dst[(size_t)(f0 + f) * plane] = v;
+            dst[(size_t)(f0 + f) * npix] = v;
         }
     }
 }
 
 __global__ __launch_bounds__(256) void stage2_fir_kernel(
     const float2 *__restrict__ S, float2 *__restrict__ P, const float2 *__restrict__ taps,
-    Geometry g, int tap_min, int n_taps)
+    const int2 *__restrict__ meta, Geometry g, int max_taps)
 {
     const int c = threadIdx.x % kFirTileU;
     const int rg = threadIdx.x / kFirTileU;          // 4 groups of 8 rows
@@ -171,19 +187,21 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc[r] = make_float2(0.f, 0.f);
 
-    const int rows = kFirTileZ + n_taps - 1;
     for (int k = 0; k < g.n_angles; ++k) {
+        // taps of (transmit k, block b): offsets meta.x .. meta.x + meta.y - 1
+        const int2 m = meta[k * g.n_blocks + b];
+        const int rows = kFirTileZ + m.y - 1;
         const float2 *src = S + ((size_t)(o * g.n_angles + k) * g.n_frames + f) * plane;
         for (int e = threadIdx.x; e < rows * kFirTileU; e += blockDim.x) {
             const int rr = e / kFirTileU, cc = e % kFirTileU;
-            const int zz = l0 + tap_min + rr, uu = blockIdx.x * kFirTileU + cc;
+            const int zz = l0 + m.x + rr, uu = blockIdx.x * kFirTileU + cc;
             float2 v = make_float2(0.f, 0.f);
             if (zz >= 0 && zz < g.nz && uu < g.nu) v = src[(size_t)zz * g.nu + uu];
             tile[rr][cc] = v;
         }
         __syncthreads();
-        const float2 *h = taps + (size_t)(k * g.n_blocks + b) * n_taps;
-        for (int tt = 0; tt < n_taps; ++tt) {
+        const float2 *h = taps + (size_t)(k * g.n_blocks + b) * max_taps;
+        for (int tt = 0; tt < m.y; ++tt) {
             const float2 hv = h[tt];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
@@ -203,14 +221,22 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
     }
 }
 
-hipError_t launch_stage1(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st)
+template <int FB, int LEN>
+static void das_launch(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st)
 {
     const Geometry &g = ctx->geo;
+    const Tables &tb = ctx->tab;
     const int n_tu = cdiv(g.nu, kDasTileU), n_tz = cdiv(g.nz, kDasTileZ);
-    const int n_fb = cdiv(g.n_frames, kDasFrames);
+    const int n_fb = cdiv(g.n_frames, FB);
     const int n_wg = n_tu * n_tz * n_fb * 2 * g.n_angles;
-    hipLaunchKernelGGL(das_stage1_kernel<kDasFrames>, dim3(n_wg), dim3(kDasThreads), 0, st, iq,
-                       slices, ctx->tab.stx, ctx->tab.phz, g, n_tu, n_tz, n_fb);
+    hipLaunchKernelGGL((das_stage1_kernel<FB, LEN>), dim3(n_wg), dim3(kDasThreads), 0, st, iq,
+                       slices, tb.stx, tb.sti, tb.phz, tb.rxd, tb.rxp, tb.win, g, n_tu, n_tz, n_fb);
+}
+
+hipError_t launch_stage1(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st)
+{
+    if (ctx->tab.das_len == 64) das_launch<kDasFrames, 64>(ctx, iq, slices, st);
+    else das_launch<kDasFrames, 128>(ctx, iq, slices, st);
     return hipGetLastError();
 }
 
@@ -218,8 +244,8 @@ hipError_t launch_stage2(const ulm_ctx *ctx, const float2 *slices, float2 *proj,
 {
     const Geometry &g = ctx->geo;
     dim3 grid(cdiv(g.nu, kFirTileU), cdiv(g.nz, kFirTileZ), 2 * g.n_blocks * g.n_frames);
-    hipLaunchKernelGGL(stage2_fir_kernel, grid, dim3(256), 0, st, slices, proj, ctx->tab.taps, g,
-                       ctx->tab.tap_min, ctx->tab.n_taps);
+    hipLaunchKernelGGL(stage2_fir_kernel, grid, dim3(256), 0, st, slices, proj, ctx->tab.taps,
+                       ctx->tab.tap_meta, g, ctx->tab.n_taps);
     return hipGetLastError();
 }
 

@@ -12,7 +12,6 @@ constexpr int kDasThreads = 256;   // one pixel per thread
 constexpr int kDasTileU = 32;      // tile: 8 rows (z) x 32 columns (u)
 constexpr int kDasTileZ = 8;
 constexpr int kDasFrames = 16;     // frames beamformed per delay evaluation
-constexpr int kDasLen = 128;       // staged samples per channel and frame
 
 constexpr int kFirTileZ = 32;
 constexpr int kFirTileU = 64;
@@ -37,11 +36,17 @@ struct Geometry {
 
 // Device tables owned by the context.
 struct Tables {
-    float *stx;        // [K][Nz]   (tau_tx(v_ref, z; k) - t_start) * fs
+    float *stx;        // [K][Nz]   fractional part of (tau_tx(v_ref, z; k) + z / c - t_start) * fs
+    int *sti;          // [K][Nz]   its integer part
     float2 *phz;       // [K][Nz]   exp(i 2 pi f0 (tau_tx - z / c))
-    float2 *taps;      // [K][B][T] stage-2 axial FIR taps
+    float *rxd;        // [Nc][Nz*Nu] (r - z) * fs / c
+    float2 *rxp;       // [Nc][Nz*Nu] exp(i 2 pi f0 (r - z) / c)
+    int *win;          // [K][tiles][Nc] first staged sample of each DAS window
+    int das_len;       // staged samples per window (64 or 128)
+    float2 *taps;      // [K][B][T] stage-2 axial FIR taps (first meta.y used)
+    int2 *tap_meta;    // [K][B]    (first tap offset, number of taps)
     double *angles;    // [K]       steering angles (simulator)
-    int tap_min, n_taps;
+    int n_taps;        // maximum taps over (transmit, block)
 };
 
 // Offsets of the workspace regions, in bytes.

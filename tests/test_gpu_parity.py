@@ -150,6 +150,15 @@ def test_ncc_parity(torch, ulm, F, nz, nu, size):
 
 
 def test_end_to_end_tiny(torch, ulm, tiny_cfg, tiny_iq):
+    """Whole path vs the oracle on the tiny ensemble.
+
+    The plain path stores projections in FP32.  The clutter filter then
+    amplifies their relative rounding (about 2e-7 after the DAS) by the
+    tissue-to-residual ratio (about 1e3 here), so the filtered planes agree to
+    about 2e-4.  Even an exactly rounded FP32 projection moves the weakest
+    detections by up to 5e-4 px in the oracle itself.  Hence two gates: 1e-3 px
+    for MB-scale peaks (envelope >= 0.2 x frame maximum), 5e-3 px for every
+    decidable detection.  The decidable detection sets must be identical."""
     cfg = tiny_cfg
     say("[end-to-end tiny] oracle pipeline")
     ref = pipeline.reconstruct_ensemble(tiny_iq, cfg)
@@ -163,9 +172,19 @@ def test_end_to_end_tiny(torch, ulm, tiny_cfg, tiny_iq):
     for o in range(2):
         e = rel_l2(filt[o, 0], ref["filtered"][o, 0])
         say(f"  filtered plane {o} rel-L2 {e:.2e}")
-        assert e <= 1e-2
-    n, nund, err = compare_detections(got, ora, N, I, cfg, delta=2e-3, pos_tol=POS_TOL)
-    say(f"  detections matched {n}, undecidable {nund}, max pos err {err:.2e}; timing {out['timing']}")
+        assert e <= 1e-3
+    n, nund, err = compare_detections(got, ora, N, I, cfg, delta=2e-3, pos_tol=5e-3)
+    strong = ora[ora["intensity"] >= 0.2 * np.array([I[r["plane"], r["block"], r["frame"]].max()
+                                                      for r in ora])]
+    g = {(int(r["plane"]), int(r["frame"]), int(r["iz"]), int(r["iu"])): r for r in got}
+    serr = 0.0
+    for r in strong:
+        k = (int(r["plane"]), int(r["frame"]), int(r["iz"]), int(r["iu"]))
+        assert k in g
+        serr = max(serr, abs(g[k]["z"] - r["z"]), abs(g[k]["u"] - r["u"]))
+    say(f"  detections matched {n}, undecidable {nund}, max pos err {err:.2e}; "
+        f"{len(strong)} MB-scale peaks, max pos err {serr:.2e}; timing {out['timing']}")
+    assert serr <= POS_TOL
 
 
 def test_sim_parity(torch, ulm, tiny_cfg, tiny_iq):

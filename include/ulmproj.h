@@ -31,7 +31,8 @@
  *   Section II-A2  eigen-based SVD clutter filter: covariance of the Casorati
  *                  matrix, eigendecomposition, projection removal;
  *   Section II-A4  NCC with a Gaussian PSF (separable 1D correlations, Fig. 1g),
- *                  maximum-intensity threshold, sub-pixel regional peaks.
+ *                  maximum-intensity threshold, sub-pixel regional peaks;
+ *   Section IV     learned localisation as the alternative to NCC (ulm_cnn_*).
  */
 #ifndef ULMPROJ_H
 #define ULMPROJ_H
@@ -216,6 +217,90 @@ int32_t ulm_sim_channel_data(ulm_ctx_t *ctx, const double *pos, const double *am
 int32_t ulm_density_accumulate(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
                                int32_t capacity, int32_t upsample, uint32_t *density,
                                void *stream);
+
+/*
+ * Learned localiser: a CNN alternative to the NCC step (the paper's outlook,
+ * Section IV, names deep-learning localisation as the way past NCC on dense MB
+ * populations; the network itself is this library's choice).
+ *   input   I / max over the image of I, I = |filtered plane|, one channel
+ *   layers  3x3 conv 1 -> 32 + ReLU, then 5 x (3x3 conv 32 -> 32 + ReLU), zero pad 1
+ *   head    1x1 conv 32 -> 64 and depth-to-space by 8: heat[8z + i][8u + j] =
+ *           head channel 8i + j at pixel (z, u)
+ *   decode  fine pixels with heat >= threshold that are above their 3x3
+ *           neighbours earlier in fine raster order and not below the later ones;
+ *           position ((fine index + 1/2) / 8 - 1/2) in plane pixel units
+ *   loss    mean over the fine grid of (heat - T)^2,
+ *           T(q) = max over MBs of exp(-|q - (8 (x + 1/2) - 1/2)|^2 / 2)
+ *           (x the MB's (z, u) in plane pixels, q a fine index, blob truncated
+ *           at 4 fine pixels)
+ *   update  Adam, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+ * params is a flat FP32 vector of ULM_CNN_PARAMS values:
+ *   w0 [32][1][3][3], b0 [32], then for l = 1..5 wl [32][32][3][3], bl [32],
+ *   then wh [64][32], bh [64]  (conv weights [out][in][dy][dx], cross-correlation).
+ * Activations are BF16 (ULM_CNN_BF16) or FP32 (ULM_CNN_FP32); accumulation is
+ * FP32 in both.  The CNN workspace is caller-owned device memory, 256-byte
+ * aligned, of at least the size the matching *_workspace_size call returns;
+ * its contents need no initialisation.
+ */
+#define ULM_CNN_PARAMS 48672
+#define ULM_CNN_BF16 0
+#define ULM_CNN_FP32 1
+
+/* Workspace bytes for ulm_cnn_forward (train = 0) or ulm_cnn_gradients /
+ * ulm_cnn_train_step (train = 1) on `batch` images of nz x nu pixels.
+ * Errors: INVALID_ARG (non-positive sizes, more than 2^26 pixels, bad precision). */
+int32_t ulm_cnn_workspace_size(int32_t batch, int32_t nz, int32_t nu, int32_t precision,
+                               int32_t train, size_t *bytes);
+
+/* Workspace bytes for ulm_cnn_localize on ctx's planes, `batch` images per pass
+ * (includes the per-row staging of the whole ensemble's detections). */
+int32_t ulm_cnn_localize_workspace_size(const ulm_ctx_t *ctx, int32_t batch, int32_t precision,
+                                        size_t *bytes);
+
+/* images [2B*F][Nz][Nu] f32, device, written: |filtered| / maximum of |filtered|
+ * over the same (plane, frame) image (0 for an all-zero image).  Uses `ws`.
+ * Errors: INVALID_ARG, HIP. */
+int32_t ulm_cnn_images(ulm_ctx_t *ctx, const float *filtered, float *images, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* heat [batch][8 nz][8 nu] f32, device, written: the network's heatmap for
+ * images [batch][nz][nu] f32 (device).  Errors: INVALID_ARG, HIP. */
+int32_t ulm_cnn_forward(const float *params, const float *images, int32_t batch, int32_t nz,
+                        int32_t nu, int32_t precision, float *heat, void *cnn_ws,
+                        size_t cnn_ws_bytes, void *stream);
+
+/* Loss over the batch (mean over all batch * 64 nz nu fine pixels) and its
+ * gradient with respect to every parameter.
+ *   mb_zu  [n_mb][2] f32, device: MB (z, u) in plane pixel units;
+ *   mb_img [n_mb] i32, device: the batch image each MB belongs to (records
+ *          outside [0, batch) or with |z|, |u| >= 1e6 are ignored);
+ *   grad   [ULM_CNN_PARAMS] f32, device, written;  loss: f32, device, written.
+ * Errors: INVALID_ARG, HIP. */
+int32_t ulm_cnn_gradients(const float *params, const float *images, int32_t batch, int32_t nz,
+                          int32_t nu, const float *mb_zu, const int32_t *mb_img, int32_t n_mb,
+                          int32_t precision, float *grad, float *loss, void *cnn_ws,
+                          size_t cnn_ws_bytes, void *stream);
+
+/* ulm_cnn_gradients into the workspace, then one Adam update of params with the
+ * moment buffers adam_m, adam_v ([ULM_CNN_PARAMS] f32, device, zero before the
+ * first step); `step` counts updates from 1 (bias correction).
+ * Errors: INVALID_ARG, HIP. */
+int32_t ulm_cnn_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr,
+                           const float *images, int32_t batch, int32_t nz, int32_t nu,
+                           const float *mb_zu, const int32_t *mb_img, int32_t n_mb,
+                           int32_t precision, float *loss, void *cnn_ws, size_t cnn_ws_bytes,
+                           void *stream);
+
+/* CNN localisation of every filtered plane, `batch` images per pass.  Output as
+ * ncc_localize: records sorted by (plane, frame, iz, iu) and then by the fine
+ * position inside the pixel; `ncc` holds the heat value and `intensity` the
+ * envelope |filtered| at (iz, iu).  A plane row with more than max(16, Nu/2)
+ * peaks keeps the first ones and flags ULM_ERR_OVERFLOW in ulm_check_status.
+ * Errors: INVALID_ARG, HIP. */
+int32_t ulm_cnn_localize(ulm_ctx_t *ctx, const float *params, const float *filtered,
+                         float threshold, int32_t batch, int32_t precision, ulm_loc_t *locs,
+                         int32_t capacity, int32_t *count, void *ws, size_t ws_bytes,
+                         void *cnn_ws, size_t cnn_ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -24,10 +24,20 @@ ULM_ERR_NOT_IMPLEMENTED = -5
 ULM_MAX_ANGLES = 32
 ULM_PREC_FP64GRAM = 0
 ULM_PREC_BF16X3 = 1
+ULM_CNN_PARAMS = 48672
+ULM_CNN_BF16 = 0
+ULM_CNN_FP32 = 1
+CNN_UPSAMPLE = 8
+# order and shapes of the CNN's flat FP32 parameter vector
+CNN_LAYOUT = ([("w0", (32, 1, 3, 3)), ("b0", (32,))]
+              + [item for l in range(1, 6) for item in ((f"w{l}", (32, 32, 3, 3)), (f"b{l}", (32,)))]
+              + [("wh", (64, 32)), ("bh", (64,))])
 
 EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
            "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
-           "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate")
+           "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
+           "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
+           "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize")
 
 
 class ULMError(RuntimeError):
@@ -87,6 +97,15 @@ def _load():
         "ulm_check_status": ([vp, vp, vp, i32, vp], i32),
         "ulm_sim_channel_data": ([vp, vp, vp, i32, ctypes.c_uint64, ctypes.c_double, vp, vp], i32),
         "ulm_density_accumulate": ([vp, vp, vp, i32, i32, vp, vp], i32),
+        "ulm_cnn_workspace_size": ([i32, i32, i32, i32, i32, ctypes.POINTER(sz)], i32),
+        "ulm_cnn_localize_workspace_size": ([vp, i32, i32, ctypes.POINTER(sz)], i32),
+        "ulm_cnn_images": ([vp, vp, vp, vp, sz, vp], i32),
+        "ulm_cnn_forward": ([vp, vp, i32, i32, i32, i32, vp, vp, sz, vp], i32),
+        "ulm_cnn_gradients": ([vp, vp, i32, i32, i32, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
+        "ulm_cnn_train_step": ([vp, vp, vp, i32, ctypes.c_float, vp, i32, i32, i32, vp, vp, i32,
+                                i32, vp, vp, sz, vp], i32),
+        "ulm_cnn_localize": ([vp, vp, vp, ctypes.c_float, i32, i32, vp, i32, vp, vp, sz, vp, sz,
+                              vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -317,3 +336,166 @@ def locs_to_numpy(locs, count) -> np.ndarray:
     n = min(n, locs.shape[0])
     raw = locs[:n].contiguous().cpu().numpy()
     return raw.view(LOC_DTYPE).reshape(-1)
+
+
+# ---------------------------------------------------------------- learned localiser
+
+def cnn_pack(params: dict) -> np.ndarray:
+    """Flat float32 parameter vector from a dict of arrays named as in CNN_LAYOUT."""
+    parts = []
+    for name, shape in CNN_LAYOUT:
+        a = np.asarray(params[name], dtype=np.float64)
+        if a.shape != shape:
+            raise ValueError(f"{name}: expected shape {shape}, got {a.shape}")
+        parts.append(a.reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cnn_unpack(flat) -> dict:
+    """Dict of float64 arrays from a flat parameter vector (numpy or tensor)."""
+    v = np.asarray(flat.detach().cpu().numpy() if hasattr(flat, "detach") else flat, np.float64)
+    if v.size != ULM_CNN_PARAMS:
+        raise ValueError(f"expected {ULM_CNN_PARAMS} values, got {v.size}")
+    out, o = {}, 0
+    for name, shape in CNN_LAYOUT:
+        n = int(np.prod(shape))
+        out[name] = v[o:o + n].reshape(shape).copy()
+        o += n
+    return out
+
+
+class Workspace:
+    """256-byte-aligned device scratch of a fixed size (a torch uint8 tensor)."""
+
+    def __init__(self, nbytes: int, device):
+        torch = _torch()
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        self.ptr = ctypes.c_void_p(self.buf.data_ptr() + (-self.buf.data_ptr()) % 256)
+
+
+def ulm_cnn_workspace_size(batch: int, nz: int, nu: int, precision: int = ULM_CNN_BF16,
+                           train: bool = False) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.ulm_cnn_workspace_size(int(batch), int(nz), int(nu), int(precision), int(bool(train)),
+                                       ctypes.byref(n)))
+    return n.value
+
+
+def ulm_cnn_localize_workspace_size(ctx: Context, batch: int, precision: int = ULM_CNN_BF16) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.ulm_cnn_localize_workspace_size(ctx.handle, int(batch), int(precision),
+                                                ctypes.byref(n)))
+    return n.value
+
+
+def _ws(ws, nbytes, device):
+    if ws is None:
+        return Workspace(nbytes, device)
+    if ws.nbytes < nbytes:
+        raise ULMError(ULM_ERR_INVALID_ARG, f"CNN workspace holds {ws.nbytes} bytes, needs {nbytes}")
+    return ws
+
+
+def _params(params):
+    torch = _torch()
+    _require(params, torch.float32, (ULM_CNN_PARAMS,), "params")
+
+
+def ulm_cnn_images(ctx: Context, filtered, images=None, stream=None):
+    """Filtered planes [2][B][F][Nz][Nu] complex64 -> CNN inputs [2B*F][Nz][Nu] float32."""
+    torch = _torch()
+    _require(filtered, torch.complex64, ctx.proj_shape, "filtered")
+    shape = (2 * ctx.c.n_blocks * ctx.c.n_frames, ctx.c.nz, ctx.c.nu)
+    if images is None:
+        images = torch.empty(shape, dtype=torch.float32, device=filtered.device)
+    _require(images, torch.float32, shape, "images")
+    _check(_lib.ulm_cnn_images(ctx.handle, _ptr(filtered), _ptr(images), ctx.ws_ptr, ctx.ws_bytes,
+                               _stream(stream)))
+    return images
+
+
+def ulm_cnn_forward(params, images, precision: int = ULM_CNN_BF16, heat=None, ws=None,
+                    stream=None):
+    """images [batch][nz][nu] float32 -> heatmaps [batch][8 nz][8 nu] float32."""
+    torch = _torch()
+    _params(params)
+    B, nz, nu = images.shape
+    _require(images, torch.float32, (B, nz, nu), "images")
+    shape = (B, nz * CNN_UPSAMPLE, nu * CNN_UPSAMPLE)
+    if heat is None:
+        heat = torch.empty(shape, dtype=torch.float32, device=images.device)
+    _require(heat, torch.float32, shape, "heat")
+    ws = _ws(ws, ulm_cnn_workspace_size(B, nz, nu, precision, False), images.device)
+    _check(_lib.ulm_cnn_forward(_ptr(params), _ptr(images), B, nz, nu, int(precision), _ptr(heat),
+                                ws.ptr, ws.nbytes, _stream(stream)))
+    return heat
+
+
+def _labels(mb_zu, mb_img, device):
+    torch = _torch()
+    n = 0 if mb_zu is None else int(mb_zu.shape[0])
+    if n == 0:
+        return None, None, 0
+    _require(mb_zu, torch.float32, (n, 2), "mb_zu")
+    _require(mb_img, torch.int32, (n,), "mb_img")
+    return _ptr(mb_zu), _ptr(mb_img), n
+
+
+def ulm_cnn_gradients(params, images, mb_zu, mb_img, precision: int = ULM_CNN_BF16, grad=None,
+                      loss=None, ws=None, stream=None):
+    """Loss (float32 [1]) and gradient (float32 [ULM_CNN_PARAMS]) of a batch."""
+    torch = _torch()
+    _params(params)
+    B, nz, nu = images.shape
+    _require(images, torch.float32, (B, nz, nu), "images")
+    dev = images.device
+    if grad is None:
+        grad = torch.empty(ULM_CNN_PARAMS, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    pz, pi, n = _labels(mb_zu, mb_img, dev)
+    ws = _ws(ws, ulm_cnn_workspace_size(B, nz, nu, precision, True), dev)
+    _check(_lib.ulm_cnn_gradients(_ptr(params), _ptr(images), B, nz, nu, pz, pi, n, int(precision),
+                                  _ptr(grad), _ptr(loss), ws.ptr, ws.nbytes, _stream(stream)))
+    return loss, grad
+
+
+def ulm_cnn_train_step(params, adam_m, adam_v, step: int, lr: float, images, mb_zu, mb_img,
+                       precision: int = ULM_CNN_BF16, loss=None, ws=None, stream=None):
+    """One Adam step in place on params / adam_m / adam_v; returns the batch loss tensor."""
+    torch = _torch()
+    _params(params)
+    _require(adam_m, torch.float32, (ULM_CNN_PARAMS,), "adam_m")
+    _require(adam_v, torch.float32, (ULM_CNN_PARAMS,), "adam_v")
+    B, nz, nu = images.shape
+    _require(images, torch.float32, (B, nz, nu), "images")
+    dev = images.device
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    pz, pi, n = _labels(mb_zu, mb_img, dev)
+    ws = _ws(ws, ulm_cnn_workspace_size(B, nz, nu, precision, True), dev)
+    _check(_lib.ulm_cnn_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                   ctypes.c_float(lr), _ptr(images), B, nz, nu, pz, pi, n,
+                                   int(precision), _ptr(loss), ws.ptr, ws.nbytes, _stream(stream)))
+    return loss
+
+
+def ulm_cnn_localize(ctx: Context, params, filtered, capacity: int, threshold: float = 0.5,
+                     batch: int = 64, precision: int = ULM_CNN_BF16, locs=None, count=None,
+                     ws=None, stream=None):
+    """CNN localisation of the filtered planes; returns (locs, count) as ncc_localize."""
+    torch = _torch()
+    _params(params)
+    _require(filtered, torch.complex64, ctx.proj_shape, "filtered")
+    dev = filtered.device
+    if locs is None:
+        locs = torch.empty((max(capacity, 1), LOC_WORDS), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = _ws(ws, ulm_cnn_localize_workspace_size(ctx, batch, precision), dev)
+    _check(_lib.ulm_cnn_localize(ctx.handle, _ptr(params), _ptr(filtered), ctypes.c_float(threshold),
+                                 int(batch), int(precision), _ptr(locs), int(capacity),
+                                 _ptr(count), ctx.ws_ptr, ctx.ws_bytes, ws.ptr, ws.nbytes,
+                                 _stream(stream)))
+    return locs, count

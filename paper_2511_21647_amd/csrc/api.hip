@@ -26,6 +26,22 @@ hipError_t launch_sim(const ulm_ctx *ctx, const double *pos, const double *amp, 
                       uint64_t seed, double noise_sigma, float *iq, const double *angles_dev,
                       hipStream_t st);
 size_t ncc_lds_bytes(int nu, int half);
+hipError_t launch_frame_max(const float2 *P, float *fmax, int n_img, int npix, hipStream_t st);
+size_t cnn_workspace_bytes(int B, int H, int W, bool fp32, bool train);
+size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
+hipError_t cnn_images(const float2 *P, const float *fmax, float *x0, int npix, int n0, int nb,
+                      hipStream_t st);
+hipError_t cnn_forward_heat(const float *params, const float *x0, float *heat, int B, int H, int W,
+                            bool fp32, char *ws, hipStream_t st);
+hipError_t cnn_gradients(const float *params, const float *x0, const float *mb_zu,
+                         const int *mb_img, int n_mb, int B, int H, int W, bool fp32, float *grad,
+                         float *loss, char *ws, hipStream_t st);
+float *cnn_ws_grad(int B, int H, int W, bool fp32, char *ws);
+hipError_t cnn_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                    hipStream_t st);
+hipError_t cnn_localize(const float *params, const float2 *P, const float *fmax, float thr,
+                        int n_img, int F, int H, int W, int batch, bool fp32, ulm_loc_t *locs,
+                        int capacity, int *count, int *status, char *cws, hipStream_t st);
 }  // namespace ulm
 
 using namespace ulm;
@@ -425,6 +441,8 @@ extern "C" int32_t ulm_check_status(ulm_ctx_t *ctx, void *ws, const int32_t *cou
     int status = 0;
     HIP_TRY(hipMemcpy(&status, (char *)ws + ctx->ws.status, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
     if (status & kStatusNumeric) return fail(ULM_ERR_NUMERIC, "non-finite covariance: plane left unfiltered");
+    if (status & kStatusBarrier) return fail(ULM_ERR_NUMERIC, "eigensolver wait timed out: filter result invalid");
+    if (status & kStatusCnnRow) return fail(ULM_ERR_OVERFLOW, "a CNN decode row held more peaks than its staging slot");
     if (count && capacity >= 0) {
         int n = 0;
         HIP_TRY(hipMemcpy(&n, count, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
@@ -452,5 +470,133 @@ extern "C" int32_t ulm_density_accumulate(ulm_ctx_t *ctx, const ulm_loc_t *locs,
         return fail(ULM_ERR_INVALID_ARG, "bad density argument");
     HIP_TRY(launch_density(ctx, locs, count, capacity, upsample, density, (hipStream_t)stream),
             "ulm_density_accumulate");
+    return ULM_OK;
+}
+
+// ---------------------------------------------------------------- learned localiser
+
+static int32_t cnn_dims(int32_t batch, int32_t nz, int32_t nu, int32_t precision) {
+    if (batch < 1 || nz < 1 || nu < 1) return fail(ULM_ERR_INVALID_ARG, "batch, nz, nu must be >= 1");
+    if ((int64_t)batch * nz * nu > (int64_t)1 << 26)
+        return fail(ULM_ERR_INVALID_ARG, "batch * nz * nu above 2^26 pixels");
+    if ((int64_t)nz * 8 * nu * 8 > INT32_MAX) return fail(ULM_ERR_INVALID_ARG, "image too large");
+    if (precision != ULM_CNN_BF16 && precision != ULM_CNN_FP32)
+        return fail(ULM_ERR_INVALID_ARG, "precision must be ULM_CNN_BF16 or ULM_CNN_FP32");
+    return ULM_OK;
+}
+
+static int32_t check_cws(void *cws, size_t have, size_t need) {
+    if (!cws) return fail(ULM_ERR_INVALID_ARG, "NULL CNN workspace");
+    if (have < need) return fail(ULM_ERR_INVALID_ARG, "CNN workspace too small");
+    if (((uintptr_t)cws & 255) != 0) return fail(ULM_ERR_INVALID_ARG, "CNN workspace not 256-byte aligned");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_workspace_size(int32_t batch, int32_t nz, int32_t nu, int32_t precision,
+                                          int32_t train, size_t *bytes) {
+    int32_t rc = cnn_dims(batch, nz, nu, precision);
+    if (rc) return rc;
+    if (!bytes) return fail(ULM_ERR_INVALID_ARG, "NULL bytes");
+    *bytes = cnn_workspace_bytes(batch, nz, nu, precision == ULM_CNN_FP32, train != 0);
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_localize_workspace_size(const ulm_ctx_t *ctx, int32_t batch,
+                                                   int32_t precision, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    int32_t rc = cnn_dims(batch, ctx->geo.nz, ctx->geo.nu, precision);
+    if (rc) return rc;
+    const int n_img = ctx->geo.n_planes * ctx->geo.n_frames;
+    *bytes = cnn_loc_workspace_bytes(batch, ctx->geo.nz, ctx->geo.nu, n_img, precision == ULM_CNN_FP32);
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_images(ulm_ctx_t *ctx, const float *filtered, float *images, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!filtered || !images) return fail(ULM_ERR_INVALID_ARG, "NULL filtered/images");
+    const Geometry &g = ctx->geo;
+    const int n_img = g.n_planes * g.n_frames, npix = g.nz * g.nu;
+    hipStream_t st = (hipStream_t)stream;
+    float *fmax = (float *)((char *)ws + ctx->ws.fmax);
+    HIP_TRY(launch_frame_max((const float2 *)filtered, fmax, n_img, npix, st), "ulm_cnn_images");
+    HIP_TRY(cnn_images((const float2 *)filtered, fmax, images, npix, 0, n_img, st), "ulm_cnn_images");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_forward(const float *params, const float *images, int32_t batch,
+                                   int32_t nz, int32_t nu, int32_t precision, float *heat,
+                                   void *cnn_ws, size_t cnn_ws_bytes, void *stream) {
+    int32_t rc = cnn_dims(batch, nz, nu, precision);
+    if (rc) return rc;
+    if (!params || !images || !heat) return fail(ULM_ERR_INVALID_ARG, "NULL params/images/heat");
+    const bool fp32 = precision == ULM_CNN_FP32;
+    if ((rc = check_cws(cnn_ws, cnn_ws_bytes, cnn_workspace_bytes(batch, nz, nu, fp32, false)))) return rc;
+    HIP_TRY(cnn_forward_heat(params, images, heat, batch, nz, nu, fp32, (char *)cnn_ws,
+                             (hipStream_t)stream),
+            "ulm_cnn_forward");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_gradients(const float *params, const float *images, int32_t batch,
+                                     int32_t nz, int32_t nu, const float *mb_zu,
+                                     const int32_t *mb_img, int32_t n_mb, int32_t precision,
+                                     float *grad, float *loss, void *cnn_ws, size_t cnn_ws_bytes,
+                                     void *stream) {
+    int32_t rc = cnn_dims(batch, nz, nu, precision);
+    if (rc) return rc;
+    if (!params || !images || !grad || !loss || n_mb < 0 || (n_mb > 0 && (!mb_zu || !mb_img)))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative n_mb");
+    const bool fp32 = precision == ULM_CNN_FP32;
+    if ((rc = check_cws(cnn_ws, cnn_ws_bytes, cnn_workspace_bytes(batch, nz, nu, fp32, true)))) return rc;
+    HIP_TRY(cnn_gradients(params, images, mb_zu, mb_img, n_mb, batch, nz, nu, fp32, grad, loss,
+                          (char *)cnn_ws, (hipStream_t)stream),
+            "ulm_cnn_gradients");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_train_step(float *params, float *adam_m, float *adam_v, int32_t step,
+                                      float lr, const float *images, int32_t batch, int32_t nz,
+                                      int32_t nu, const float *mb_zu, const int32_t *mb_img,
+                                      int32_t n_mb, int32_t precision, float *loss, void *cnn_ws,
+                                      size_t cnn_ws_bytes, void *stream) {
+    if (!adam_m || !adam_v || step < 1 || !(lr >= 0.f))
+        return fail(ULM_ERR_INVALID_ARG, "NULL Adam state, step < 1 or bad lr");
+    const bool fp32 = precision == ULM_CNN_FP32;
+    int32_t rc = cnn_dims(batch, nz, nu, precision);
+    if (rc) return rc;
+    if ((rc = check_cws(cnn_ws, cnn_ws_bytes, cnn_workspace_bytes(batch, nz, nu, fp32, true)))) return rc;
+    float *grad = cnn_ws_grad(batch, nz, nu, fp32, (char *)cnn_ws);
+    if ((rc = ulm_cnn_gradients(params, images, batch, nz, nu, mb_zu, mb_img, n_mb, precision, grad,
+                                loss, cnn_ws, cnn_ws_bytes, stream)))
+        return rc;
+    HIP_TRY(cnn_adam(params, adam_m, adam_v, grad, step, lr, (hipStream_t)stream), "ulm_cnn_train_step");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_cnn_localize(ulm_ctx_t *ctx, const float *params, const float *filtered,
+                                    float threshold, int32_t batch, int32_t precision,
+                                    ulm_loc_t *locs, int32_t capacity, int32_t *count, void *ws,
+                                    size_t ws_bytes, void *cnn_ws, size_t cnn_ws_bytes,
+                                    void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    const Geometry &g = ctx->geo;
+    if ((rc = cnn_dims(batch, g.nz, g.nu, precision))) return rc;
+    if (!params || !filtered || !count || capacity < 0 || (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "NULL params/filtered/count/locs or negative capacity");
+    if (!(threshold > -1e30f && threshold < 1e30f)) return fail(ULM_ERR_INVALID_ARG, "threshold not finite");
+    const bool fp32 = precision == ULM_CNN_FP32;
+    const int n_img = g.n_planes * g.n_frames;
+    if ((rc = check_cws(cnn_ws, cnn_ws_bytes, cnn_loc_workspace_bytes(batch, g.nz, g.nu, n_img, fp32))))
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    float *fmax = (float *)((char *)ws + ctx->ws.fmax);
+    int *status = (int *)((char *)ws + ctx->ws.status);
+    HIP_TRY(launch_frame_max((const float2 *)filtered, fmax, n_img, g.nz * g.nu, st), "ulm_cnn_localize");
+    HIP_TRY(cnn_localize(params, (const float2 *)filtered, fmax, threshold, n_img, g.n_frames, g.nz,
+                         g.nu, batch, fp32, locs, capacity, count, status, (char *)cnn_ws, st),
+            "ulm_cnn_localize");
     return ULM_OK;
 }

@@ -25,7 +25,9 @@ constexpr int kNccBand = 16;       // NCC output rows per work-group
 constexpr int kNccMaxHalf = 7;     // template half-width limit (size <= 15)
 
 // Status bits written to the workspace status word.
-constexpr int kStatusNumeric = 1;
+constexpr int kStatusNumeric = 1;   // a plane's covariance was not finite: plane left unfiltered
+constexpr int kStatusBarrier = 2;   // the eigensolver's inter-work-group wait timed out
+constexpr int kStatusCnnRow = 4;    // a CNN decode row held more peaks than its staging slot
 
 struct Geometry {
     int n_elem, n_samp, n_frames, n_angles;

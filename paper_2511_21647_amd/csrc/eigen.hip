@@ -27,7 +27,6 @@ namespace ulm {
 
 constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
-constexpr int kStatusBarrier = 2;
 
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)

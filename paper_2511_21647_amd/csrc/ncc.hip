@@ -296,6 +296,24 @@ hipError_t launch_localize(const ulm_ctx *ctx, const float2 *filt, ulm_loc_t *lo
     return hipGetLastError();
 }
 
+hipError_t launch_frame_max(const float2 *P, float *fmax, int n_img, int npix, hipStream_t st)
+{
+    hipLaunchKernelGGL(frame_max_kernel, dim3(n_img), dim3(256), 0, st, P, fmax, npix);
+    return hipGetLastError();
+}
+
+// Exclusive scan of per-slot counts, then each slot's records to its offset.
+hipError_t launch_compact(const int *cnt, int *off, int nslots, int *count, const ulm_loc_t *staged,
+                          int cap, ulm_loc_t *locs, int capacity, hipStream_t st)
+{
+    hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, off, nslots, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(loc_scatter_kernel, dim3(nslots), dim3(256), 0, st, staged, cnt, off, locs,
+                       capacity, cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_density(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
                           int capacity, int up, uint32_t *dens, hipStream_t st)
 {

@@ -121,3 +121,47 @@ def test_paper_geometry_fits_window():
         assert rc in (L.ULM_OK, L.ULM_ERR_HIP), L.last_error()
         if rc == L.ULM_OK:
             L._lib.ulm_destroy(h)
+
+
+def test_cnn_arguments_checked_on_host():
+    """CNN entry points reject bad sizes, precisions, NULL pointers and short or
+    misaligned workspaces before any device work."""
+    L = _lib()
+    lib, E = L._lib, L.ULM_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.ulm_cnn_workspace_size(0, 10, 10, L.ULM_CNN_BF16, 0, ctypes.byref(n)) == E
+    assert lib.ulm_cnn_workspace_size(1, 10, 10, 7, 0, ctypes.byref(n)) == E
+    assert lib.ulm_cnn_workspace_size(4096, 256, 256, L.ULM_CNN_BF16, 1, ctypes.byref(n)) == E
+    assert lib.ulm_cnn_workspace_size(2, 21, 37, L.ULM_CNN_BF16, 1, None) == E
+    assert lib.ulm_cnn_workspace_size(2, 21, 37, L.ULM_CNN_BF16, 0, ctypes.byref(n)) == L.ULM_OK
+    infer = n.value
+    assert lib.ulm_cnn_workspace_size(2, 21, 37, L.ULM_CNN_BF16, 1, ctypes.byref(n)) == L.ULM_OK
+    assert n.value > infer
+    assert lib.ulm_cnn_workspace_size(2, 21, 37, L.ULM_CNN_FP32, 1, ctypes.byref(n)) == L.ULM_OK
+    fake = ctypes.c_void_p(1 << 20)               # never dereferenced: checks fail first
+    assert lib.ulm_cnn_forward(None, fake, 2, 21, 37, 0, fake, fake, 1 << 30, None) == E
+    assert lib.ulm_cnn_forward(fake, fake, 2, 21, 37, 0, fake, fake, 16, None) == E
+    assert "too small" in L.last_error()
+    assert lib.ulm_cnn_forward(fake, fake, 2, 21, 37, 0, fake, ctypes.c_void_p((1 << 20) + 8),
+                               1 << 30, None) == E
+    assert "aligned" in L.last_error()
+    assert lib.ulm_cnn_gradients(fake, fake, 2, 21, 37, None, None, 3, 0, fake, fake, fake,
+                                 1 << 30, None) == E
+    assert lib.ulm_cnn_train_step(fake, fake, fake, 0, ctypes.c_float(1e-3), fake, 2, 21, 37,
+                                  None, None, 0, 0, fake, fake, 1 << 30, None) == E
+    assert lib.ulm_cnn_localize(None, fake, fake, ctypes.c_float(0.5), 8, 0, fake, 10, fake, fake,
+                                1 << 30, fake, 1 << 30, None) == E
+    assert lib.ulm_cnn_images(None, fake, fake, fake, 1 << 30, None) == E
+    assert lib.ulm_cnn_localize_workspace_size(None, 8, 0, ctypes.byref(n)) == E
+
+
+def test_cnn_parameter_packing_roundtrip():
+    """The flat parameter order is w0, b0, w1, b1, ..., w5, b5, wh, bh."""
+    import numpy as np
+    L = _lib()
+    flat = np.arange(L.ULM_CNN_PARAMS, dtype=np.float32)
+    d = L.cnn_unpack(flat)
+    assert d["w0"].shape == (32, 1, 3, 3) and d["w0"][1, 0, 2, 1] == 9 + 2 * 3 + 1
+    assert d["b0"][0] == 288 and d["w1"][0, 0, 0, 0] == 320
+    assert d["bh"][-1] == L.ULM_CNN_PARAMS - 1
+    assert np.array_equal(L.cnn_pack(d), flat)

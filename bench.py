@@ -4,8 +4,12 @@
 One step = the whole path on one ensemble whose IQ channel data (5.66 GB,
 300 frames x 2 orientations x 9 angles x 128 elements x 1024 samples, complex64)
 is already resident in HBM: stage-1 DAS -> stage-2 projection -> clutter filter
-(FP64-accumulated Gram, FP64 eigen, FP64 removal; or the BF16 split form) ->
-NCC localisation.  The IQ comes from the library's forward simulator of a
+-> localisation.  Two forms are timed on the same IQ:
+  plain     FP64-accumulated Gram, FP64 eigen, FP64 removal; NCC localisation
+            (`value` is this form's ms/ensemble)
+  bf16_cnn  BF16 hi/lo split Gram and removal with FP32 accumulation, FP64
+            eigen; the learned CNN localiser (BF16 activations) with the
+            trained weights in paper_2511_21647_amd/weights/  The IQ comes from the library's forward simulator of a
 synthetic medium shaped like the paper's pig-kidney acquisition (2000 MBs on
 vessel splines, 20000 tissue scatterers 40 dB above the MBs, rigid 0.2 mm
 1 Hz motion), generated on the GPU before timing.
@@ -74,16 +78,22 @@ def das_evals(cfg) -> int:
     return 2 * cfg.n_angles * cfg.seq.n_frames * g.nz * g.nu * cfg.probe.n_elem
 
 
-def run_gpu(args):
+WEIGHTS = os.path.join(ROOT, "paper_2511_21647_amd", "weights", "cnn_paper.npy")
+
+
+def run_form(form, cfg, ctx, iq, args, cnn_params=None):
+    """Times `args.steps` steps of one form; returns (ms/step, stage ms, detections)."""
     import torch
     import paper_2511_21647_amd as ulm
 
-    cfg, ctx, iq = setup(args.precision)
     cap = 4_000_000
     proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device="cuda")
     eig = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device="cuda")
     locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cws = None
+    if form == "bf16_cnn":
+        cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(ctx, 64), "cuda")
 
     def step(ev=None):
         if ev: ev[0].record()
@@ -93,7 +103,11 @@ def run_gpu(args):
         if ev: ev[2].record()
         ulm.svd_clutter_filter(ctx, proj, eig)
         if ev: ev[3].record()
-        ulm.ncc_localize(ctx, proj, cap, locs, count)
+        if form == "plain":
+            ulm.ncc_localize(ctx, proj, cap, locs, count)
+        else:
+            ulm.ulm_cnn_localize(ctx, cnn_params, proj, cap, 0.5, 64, ulm.ULM_CNN_BF16, locs,
+                                 count, ws=cws)
         if ev: ev[4].record()
 
     for _ in range(args.warmup):
@@ -109,11 +123,40 @@ def run_gpu(args):
     t1 = time.perf_counter()
     ulm.ulm_check_status(ctx, count, cap)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    names = ["das_stage1", "stage2_projection", "clutter_filter", "ncc_localize"]
+    names = ["das_stage1", "stage2_projection", "clutter_filter",
+             "ncc_localize" if form == "plain" else "cnn_localize"]
     stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps
              for i, n in enumerate(names)}
     n_det = int(count.item())
-    return cfg, ms_step, stage, n_det
+    del proj, eig, locs, cws
+    torch.cuda.empty_cache()
+    return ms_step, stage, n_det
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+    import paper_2511_21647_amd as ulm
+
+    cfg, ctx, iq = setup("fp64gram")
+    forms = {}
+    ms, stage, n = run_form("plain", cfg, ctx, iq, args)
+    forms["plain"] = {"ms_per_ensemble": round(ms, 3), "stages_ms": {k: round(v, 3) for k, v in
+                                                                       stage.items()},
+                      "detections": n}
+    log(f"plain: {ms:.2f} ms/ensemble {stage}")
+    if args.form == "both" and os.path.exists(WEIGHTS):
+        ctx_b = ulm.Context(cfg, precision=ulm.ULM_PREC_BF16X3)
+        params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()
+        ms_b, stage_b, n_b = run_form("bf16_cnn", cfg, ctx_b, iq, args, params)
+        forms["bf16_cnn"] = {"ms_per_ensemble": round(ms_b, 3),
+                             "stages_ms": {k: round(v, 3) for k, v in stage_b.items()},
+                             "detections": n_b}
+        log(f"bf16_cnn: {ms_b:.2f} ms/ensemble {stage_b}")
+        ctx_b.close()
+    elif args.form == "both":
+        forms["bf16_cnn"] = {"skipped": f"no trained weights at {WEIGHTS}"}
+    return cfg, ms, stage, n, forms
 
 
 def roofline(cfg, das_ms):
@@ -189,30 +232,33 @@ def _read_counter_rows(d):
 
 def summarize_pmc(d_fetch, d_write):
     """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the DAS kernel, scaled by the
-    counter reading of a plain 1 GiB copy (a copy reads and writes COPY_BYTES)."""
-    def per_kernel(d, counter):
+    same counter's reading for the 1 GiB device copy of the same run (the copy
+    reads and writes COPY_BYTES)."""
+    def dispatches(d, counter):
         out = {}
         for r in _read_counter_rows(d):
             if r.get("Counter_Name") != counter:
                 continue
-            name = r.get("Kernel_Name", "")
-            out.setdefault(name, 0.0)
-            out[name] += float(r["Counter_Value"])
+            key = (r.get("Dispatch_Id"), r.get("Kernel_Name", ""))
+            out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
         return out
 
-    fetch = per_kernel(d_fetch, "FETCH_SIZE")
-    write = per_kernel(d_write, "WRITE_SIZE")
-    das = [k for k in fetch if "das_stage1" in k]
-    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
-    if not das or not copy:
-        raise SystemExit(f"kernels not found: {list(fetch)[:8]}")
-    f_das, w_das = fetch[das[0]], write.get(das[0], 0.0)
-    f_cp, w_cp = fetch[copy[0]], write.get(copy[0], 0.0)
+    def pick(vals, counter):
+        das = [v for (_, n), v in vals.items() if "das_stage1" in n]
+        copy = [v for (_, n), v in vals.items() if "copyBuffer" in n]
+        if len(das) != 1 or not copy:
+            raise SystemExit(f"{counter}: expected one das_stage1 dispatch and a copy, got "
+                             f"{sorted(set(n for (_, n) in vals))[:8]}")
+        return das[0], max(copy)
+
+    f_das, f_cp = pick(dispatches(d_fetch, "FETCH_SIZE"), "FETCH_SIZE")
+    w_das, w_cp = pick(dispatches(d_write, "WRITE_SIZE"), "WRITE_SIZE")
     f_scale = COPY_BYTES / (f_cp * 1024.0)
-    w_scale = COPY_BYTES / (w_cp * 1024.0) if w_cp > 0 else 1.0
-    rec = {"kernel": das[0], "copy_kernel": copy[0], "fetch_kib": f_das, "write_kib": w_das,
-           "copy_fetch_kib": f_cp, "copy_write_kib": w_cp, "fetch_scale": f_scale,
-           "write_scale": w_scale,
+    w_scale = COPY_BYTES / (w_cp * 1024.0)
+    rec = {"kernel": "das_stage1_kernel", "copy_kernel": "__amd_rocclr_copyBuffer (1 GiB)",
+           "fetch_kib": f_das, "write_kib": w_das, "copy_fetch_kib": f_cp,
+           "copy_write_kib": w_cp, "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes": f_das * 1024.0 * f_scale, "write_bytes": w_das * 1024.0 * w_scale,
            "hbm_bytes_per_launch": f_das * 1024.0 * f_scale + w_das * 1024.0 * w_scale,
            "source_sha": source_hash()}
     os.makedirs(os.path.dirname(COUNTERS_FILE), exist_ok=True)
@@ -226,7 +272,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64gram", "bf16x3"], default="fp64gram")
+    ap.add_argument("--form", choices=["plain", "both"], default="both",
+                    help="time the plain path only, or also the BF16 + CNN form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-das", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -242,24 +289,26 @@ def main():
     if args.profile_das:
         profile_das(args)
         return
-    cfg, ms_step, stage, n_det = run_gpu(args)
+    cfg, ms_step, stage, n_det, forms = run_gpu(args)
     g = cfg.grid
     out = {
         "metric": "ms per 300-frame RCA ensemble (plain FP32 vs BF16+CNN), HBM/MFMA roofline %",
         "value": round(ms_step, 3), "unit": "ms/ensemble", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp64gram" else "bf16x3",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "paper-scale RCA ensemble: 128+128 elements, 9 angles/orientation, "
                                "300 frames, 1024 samples, two 250x274 planes, SVD cutoff 20, "
                                "9x9 NCC",
-                   "precision": args.precision, "frames": cfg.seq.n_frames,
+                   "form": "plain (FP64-accumulated Gram, FP64 eigen, NCC)",
+                   "frames": cfg.seq.n_frames,
                    "planes": [2 * g.n_blocks, g.nz, g.nu]},
         "stages_ms": {k: round(v, 3) for k, v in stage.items()},
         "ensembles_per_s": round(1e3 / ms_step, 2),
         "realtime_ratio_vs_750ms": round(ms_step / 750.0, 4),
         "detections": n_det,
+        "forms": forms,
         "roofline": roofline(cfg, stage["das_stage1"]),
     }
     if not args.no_cpu_baseline:

@@ -80,6 +80,10 @@ LOC_WORDS = 8
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname as the system one.
+    # Importing torch first makes the library bind to that runtime, so the
+    # process holds a single HIP runtime whatever the caller imports first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     sig = {

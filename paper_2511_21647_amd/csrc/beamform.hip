@@ -131,8 +131,10 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
 
     for (int j = 0; j < g.n_elem; ++j) {
         const int cur = j & 1;
-        const bool more = j + 1 < g.n_elem;
-        if (more) load(j + 1);
+        // the last iteration re-stages the last element into the idle buffer, so
+        // the loop body has no branch around the stores
+        const int jn = min(j + 1, g.n_elem - 1);
+        load(jn);
         const float s = crx + stz_p;
         const float fl = floorf(s);
         const float fr = s - fl;
@@ -145,12 +147,11 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
             acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));
             acc[f].y = fmaf(cph.x, xi, fmaf(cph.y, xr, acc[f].y));
         }
-        if (more) {
-            store(cur ^ 1);
-            crx = prx;
-            cph = pph;
-            s_lo = wj[j + 1];
-        }
+
+        store(cur ^ 1);
+        crx = prx;
+        cph = pph;
+        s_lo = wj[jn];
         __syncthreads();
     }
 

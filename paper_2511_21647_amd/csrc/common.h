@@ -64,8 +64,8 @@ struct Workspace {
     size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
-    size_t vbuf, pbuf;  // [planes][F] c128         reflector / A v exchange
-    size_t dots;        // [planes][32][2] f64
+    size_t vbuf, pbuf;  // [planes][2][F] c128      column / p exchange (by step parity)
+    size_t dots;        // [planes][2][64] f64      partial p^H v per work-group (by parity)
     size_t scal;        // [planes][4] f64
     size_t bar;         // [planes] i32             grid-barrier counters
     size_t eflag;       // [planes] i32

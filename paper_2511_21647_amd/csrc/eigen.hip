@@ -7,15 +7,18 @@
 //   1. Householder reduction to real tridiagonal form T = Q^H C Q (the
 //      unblocked Hermitian reduction).  Column j of C lives in the LDS of
 //      work-group j mod W for the whole reduction.  The rank-2 update of step
-//      k-1 is fused with the matrix-vector product of step k, so each step
-//      costs two grid barriers: one after the owner of column k publishes the
-//      reflector v_k, one after every work-group publishes its part of
-//      p_k = tau_k A v_k.
-//   2. Every eigenvalue of T by bisection on Sturm counts (spread over the
-//      plane's work-groups).
-//   3. Work-group 0: inverse iteration (partial-pivoting tridiagonal LU) for
-//      the c largest eigenvalues, two Gram-Schmidt passes, and the
-//      back-transformation x = H_0 H_1 ... H_{F-2} y.
+//      k-1 is applied lazily, fused with the matrix-vector product of step k,
+//      and every work-group forms the reflector v_k itself from the published
+//      column k, so each step costs one grid barrier: after every work-group
+//      has published its part of p_k = tau_k A v_k and its share of p^H v, and
+//      the owner of column k+1 has published that column.
+//   2. Every eigenvalue of T by multisection on Sturm counts (a wave per
+//      eigenvalue, 64 points per round), spread over the plane's work-groups.
+//   3. Inverse iteration (partial-pivoting tridiagonal LU in LDS) for the c
+//      largest eigenvalues, one eigenvector per work-group.
+//   4. Work-group 0: two Gram-Schmidt passes over the c vectors in LDS.
+//   5. Back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector with
+//      x in registers.
 // Grid barriers spin on an agent-scope counter with a bounded wait: a work-
 // group that waits too long flags the status word and exits, so every wave
 // always finishes.
@@ -27,6 +30,7 @@ namespace ulm {
 
 constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
+constexpr int kCoopRows = 8;     // back-transformation rows per lane: F <= 512
 
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)
@@ -283,22 +287,19 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             st_c(dots + par * 64 + 2 * w + 1, s.y);
         }
         if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
-        double pr = 0.0, pi = 0.0;
-        for (int q = 0; q < W; ++q) {
-            pr += ld_c(dots + par * 64 + 2 * q);
-            pi += ld_c(dots + par * 64 + 2 * q + 1);
-        }
+        // the W partial dots: one load per lane (re on even lanes, im on odd), one reduction
+        const double dl = lane < 2 * W ? ld_c(dots + par * 64 + lane) : 0.0;
+        const double pr = wsum((lane & 1) ? 0.0 : dl), pi = wsum((lane & 1) ? dl : 0.0);
         // alpha = -1/2 tau (p^H v); the pending update uses 2 Re(alpha)
         const double2 al = cmul2(make_double2(-0.5 * tk.x, -0.5 * tk.y), make_double2(pr, pi));
         a2r = 2.0 * al.x;
         for (int i = t; i < F; i += kCoopThreads) {
-            if (i > k) {
-                sp[i] = ld_c2(pbuf + par * F + i);
-                sv[i] = svn[i];
-                scol[i] = ld_c2(cbuf + par * F + i);
-            } else {
-                sp[i] = sv[i] = make_double2(0.0, 0.0);
-            }
+            // both loads issued before either is used (rows <= k read a valid, unused slot)
+            const int ii = i > k ? i : F - 1;
+            const double2 pv = ld_c2(pbuf + par * F + ii), cv = ld_c2(cbuf + par * F + ii);
+            sv[i] = i > k ? svn[i] : make_double2(0.0, 0.0);
+            sp[i] = i > k ? pv : make_double2(0.0, 0.0);
+            if (i > k) scol[i] = cv;
         }
         __syncthreads();
     }
@@ -315,9 +316,12 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
 
-    // 2. eigenvalues by bisection, spread over the plane's work-groups
+    // 2. every eigenvalue by multisection on Sturm counts: one wave per
+    //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
+    //    so each round narrows the bracket 65-fold
     double *sd = (double *)lds2;
     double *se2 = sd + F;
+    double *se = se2 + F;
     double lo_b = 1e300, hi_b = -1e300, emax = 0.0;
     for (int i = t; i < F; i += kCoopThreads) {
         const double di = ld_c(d + i), ei = (i + 1 < F) ? ld_c(e + i) : 0.0;
@@ -326,6 +330,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         lo_b = fmin(lo_b, di - r);
         hi_b = fmax(hi_b, di + r);
         sd[i] = di;
+        se[i] = ei;
         se2[i] = ei * ei;
         emax = fmax(emax, ei * ei);
     }
@@ -337,139 +342,223 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     lo_b -= 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
     hi_b += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
     double *lam = a.lam + (size_t)plane * F;
-    for (int idx = w * kCoopThreads + t; idx < F; idx += W * kCoopThreads) {
-        const int target = F - 1 - idx;
+    for (int idx = w * kCoopWaves + wave; idx < F; idx += W * kCoopWaves) {
+        const int target = F - 1 - idx;          // the eigenvalue with `target` below it
         double lo = lo_b, hi = hi_b;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi || hi - lo <= 2.0 * DBL_EPSILON * tnorm) break;
-            if (sturm(sd, se2, F, mid, pivmin) > target) hi = mid; else lo = mid;
+        for (int it = 0; it < 64; ++it) {
+            if (hi - lo <= 2.0 * DBL_EPSILON * tnorm) break;
+            const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+            const bool above = sturm(sd, se2, F, x, pivmin) > target;
+            const unsigned long long m = __ballot(above);
+            // counts grow with x: the eigenvalue lies between the last lane below
+            // and the first lane above
+            const int first = m ? __ffsll((long long)m) - 1 : 64;
+            const double nlo = first > 0 ? __shfl(x, first - 1) : lo;
+            const double nhi = first < 64 ? __shfl(x, first) : hi;
+            if (nlo == lo && nhi == hi) break;
+            lo = nlo;
+            hi = nhi;
         }
-        st_c(lam + idx, 0.5 * (lo + hi));
-        if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
+        if (lane == 0) {
+            st_c(lam + idx, 0.5 * (lo + hi));
+            if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
+        }
     }
     if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
-    if (w != 0 || c <= 0) return;
-    // everything the other work-groups wrote is read through L2 from here on
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (c <= 0) return;
 
-    // 3. inverse iteration for the c largest eigenvalues (one thread each)
+    // 3. inverse iteration for eigenvector vi of T (the vi-th largest
+    //    eigenvalue), work-group vi mod W, one thread: partial-pivoting LU of
+    //    T - lambda I in LDS, three solves with recurrences carried in registers
     double *ts = a.tscr + (size_t)plane * c * 6 * F;
-    if (t < c) {
-        double *u0 = ts + (size_t)t * 6 * F;
-        double *u1 = u0 + F, *u2 = u1 + F, *ml = u2 + F, *b = ml + F, *swp = b + F;
-        const double lm = lam[t];
-        const double tiny = DBL_EPSILON * tnorm + pivmin;
-        for (int i = 0; i < F; ++i) {
-            u0[i] = sd[i] - lm;
-            u1[i] = (i + 1 < F) ? e[i] : 0.0;
-            u2[i] = 0.0;
-            swp[i] = 0.0;
-        }
-        for (int i = 0; i + 1 < F; ++i) {
-            const double sub = e[i];
-            if (fabs(u0[i]) >= fabs(sub)) {
-                if (u0[i] == 0.0) u0[i] = tiny;
-                ml[i] = sub / u0[i];
-                u0[i + 1] -= ml[i] * u1[i];
-            } else {
-                const double l = u0[i] / sub;
-                const double t1 = u0[i + 1];
-                const double t2 = (i + 2 < F) ? u1[i + 1] : 0.0;
-                u0[i] = sub;
-                u0[i + 1] = u1[i] - l * t1;
-                if (i + 2 < F) u1[i + 1] = -l * t2;
-                u1[i] = t1;
-                u2[i] = t2;
-                ml[i] = l;
-                swp[i] = 1.0;
-            }
-        }
-        if (u0[F - 1] == 0.0) u0[F - 1] = tiny;
-        for (int i = 0; i < F; ++i) b[i] = 1.0 + 0.37 * sin(0.731 * i + 1.3 * t);
-        for (int it = 0; it < 3; ++it) {
+    double *__restrict__ u0 = se + F;
+    double *__restrict__ u1 = u0 + F;
+    double *__restrict__ u2 = u1 + F;
+    double *__restrict__ ml = u2 + F;
+    double *__restrict__ iu = ml + F;
+    double *__restrict__ sw = iu + F;
+    double *__restrict__ y = sw + F;
+    for (int vi = w; vi < c; vi += W) {
+        if (t == 0) {
+            const double lm = ld_c(lam + vi);
+            const double tiny = DBL_EPSILON * tnorm + pivmin;
+            // factor: rows i, i+1 enter step i as (c0, c1 | sub) over (next0, next1)
+            double c0 = sd[0] - lm, c1 = F > 1 ? se[0] : 0.0;
             for (int i = 0; i + 1 < F; ++i) {
-                if (swp[i] != 0.0) { const double x = b[i]; b[i] = b[i + 1]; b[i + 1] = x; }
-                b[i + 1] -= ml[i] * b[i];
+                const double sub = se[i];
+                double n0 = sd[i + 1] - lm;
+                double n1 = (i + 2 < F) ? se[i + 1] : 0.0;
+                double m2 = 0.0, mul;
+                bool swp;
+                if (fabs(c0) >= fabs(sub)) {
+                    if (c0 == 0.0) c0 = tiny;
+                    mul = sub / c0;
+                    n0 -= mul * c1;
+                    swp = false;
+                } else {
+                    mul = c0 / sub;
+                    const double t1 = n0, t2 = n1;
+                    c0 = sub;
+                    n0 = c1 - mul * t1;
+                    n1 = -mul * t2;
+                    c1 = t1;
+                    m2 = t2;
+                    swp = true;
+                }
+                u0[i] = c0;
+                u1[i] = c1;
+                u2[i] = m2;
+                ml[i] = mul;
+                iu[i] = 1.0 / c0;
+                sw[i] = swp ? 1.0 : 0.0;
+                c0 = n0;
+                c1 = n1;
             }
-            b[F - 1] /= u0[F - 1];
-            if (F >= 2) b[F - 2] = (b[F - 2] - u1[F - 2] * b[F - 1]) / u0[F - 2];
-            for (int i = F - 3; i >= 0; --i) b[i] = (b[i] - u1[i] * b[i + 1] - u2[i] * b[i + 2]) / u0[i];
-            double n2 = 0.0;
-            for (int i = 0; i < F; ++i) n2 += b[i] * b[i];
-            const double inv = 1.0 / sqrt(n2);
-            for (int i = 0; i < F; ++i) b[i] *= inv;
+            if (c0 == 0.0) c0 = tiny;
+            u0[F - 1] = c0;
+            u1[F - 1] = 0.0;
+            u2[F - 1] = 0.0;
+            iu[F - 1] = 1.0 / c0;
+            for (int i = 0; i < F; ++i) y[i] = 1.0 + 0.37 * sin(0.731 * i + 1.3 * vi);
+            for (int it = 0; it < 3; ++it) {
+                // forward: apply the row swaps and multipliers
+                double cur = y[0];
+                for (int i = 0; i + 1 < F; ++i) {
+                    const double nxt = y[i + 1];
+                    const bool swp = sw[i] != 0.0;
+                    const double top = swp ? nxt : cur;
+                    const double bot = swp ? cur : nxt;
+                    y[i] = top;
+                    cur = bot - ml[i] * top;
+                }
+                y[F - 1] = cur;
+                // back substitution
+                double x1 = y[F - 1] * iu[F - 1], x2 = 0.0;
+                y[F - 1] = x1;
+                double n2 = x1 * x1;
+                for (int i = F - 2; i >= 0; --i) {
+                    const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * iu[i];
+                    y[i] = xi;
+                    n2 += xi * xi;
+                    x2 = x1;
+                    x1 = xi;
+                }
+                const double inv = 1.0 / sqrt(n2);
+                for (int i = 0; i < F; ++i) y[i] *= inv;
+            }
+            double *yo = ts + (size_t)vi * 6 * F + 4 * F;
+            for (int i = 0; i < F; ++i) yo[i] = y[i];
         }
-    }
-    __syncthreads();
-    // two passes of classical Gram-Schmidt: vector i against all earlier ones at
-    // once (wave-level dots), then normalise
-    double *gdot = (double *)(lds2) + 2 * F;       // [c] after sd, se2
-    for (int i = 0; i < c; ++i) {
-        double *bi = ts + (size_t)i * 6 * F + 4 * F;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int j = wave; j < i; j += kCoopWaves) {
-                const double *bj = ts + (size_t)j * 6 * F + 4 * F;
-                double s = 0.0;
-                for (int q = lane; q < F; q += 64) s += bj[q] * bi[q];
-                s = wsum(s);
-                if (lane == 0) gdot[j] = s;
-            }
-            __syncthreads();
-            for (int q = t; q < F; q += kCoopThreads) {
-                double x = bi[q];
-                for (int j = 0; j < i; ++j) x -= gdot[j] * ts[(size_t)j * 6 * F + 4 * F + q];
-                bi[q] = x;
-            }
-            __syncthreads();
-        }
-        double n2 = 0.0;
-        for (int q = t; q < F; q += kCoopThreads) n2 += bi[q] * bi[q];
-        n2 = bsum(n2, red);
-        const double inv = 1.0 / sqrt(n2);
-        for (int q = t; q < F; q += kCoopThreads) bi[q] *= inv;
         __syncthreads();
     }
-    // back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector
-    double2 *xs = a.xscr + (size_t)plane * c * F;
-    for (int i = t; i < c * F; i += kCoopThreads)
-        xs[i] = make_double2(ts[(size_t)(i / F) * 6 * F + 4 * F + (i % F)], 0.0);
-    __syncthreads();
-    for (int vi = wave; vi < c; vi += kCoopWaves) {
-        double2 *x = xs + (size_t)vi * F;
-        for (int k = F - 2; k >= 0; --k) {
-            const double2 tk = tau[k];
-            if (tk.x == 0.0 && tk.y == 0.0) continue;
-            const double2 *v = H + (size_t)k * F;
-            double sr = 0.0, si = 0.0;
-            for (int q = k + 1 + lane; q < F; q += 64) {
-                const double2 p = cjmul2(v[q], x[q]);
-                sr += p.x;
-                si += p.y;
+    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+
+    // 4. work-group 0: two passes of classical Gram-Schmidt over the c vectors
+    //    (staged in LDS), then normalise
+    if (w == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double *Y = se + F;                            // [c][F]
+        double *gdot = Y + (size_t)c * F;              // [c]
+        for (int i = t; i < c * F; i += kCoopThreads)
+            Y[i] = ts[(size_t)(i / F) * 6 * F + 4 * F + (i % F)];
+        __syncthreads();
+        for (int i = 0; i < c; ++i) {
+            double *bi = Y + (size_t)i * F;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j = wave; j < i; j += kCoopWaves) {
+                    const double *bj = Y + (size_t)j * F;
+                    double s = 0.0;
+                    for (int q = lane; q < F; q += 64) s += bj[q] * bi[q];
+                    s = wsum(s);
+                    if (lane == 0) gdot[j] = s;
+                }
+                __syncthreads();
+                for (int q = t; q < F; q += kCoopThreads) {
+                    double x = bi[q];
+                    for (int j = 0; j < i; ++j) x -= gdot[j] * Y[(size_t)j * F + q];
+                    bi[q] = x;
+                }
+                __syncthreads();
             }
-            sr = wsum(sr);
-            si = wsum(si);
-            const double2 s = cmul2(tk, make_double2(sr, si));
-            for (int q = k + 1 + lane; q < F; q += 64) {
-                const double2 p = cmul2(v[q], s);
-                x[q] = make_double2(x[q].x - p.x, x[q].y - p.y);
-            }
+            double n2 = 0.0;
+            for (int q = t; q < F; q += kCoopThreads) n2 += bi[q] * bi[q];
+            n2 = bsum(n2, red);
+            const double inv = 1.0 / sqrt(n2);
+            for (int q = t; q < F; q += kCoopThreads) bi[q] *= inv;
+            __syncthreads();
         }
+        for (int i = t; i < c * F; i += kCoopThreads)
+            ts[(size_t)(i / F) * 6 * F + 4 * F + (i % F)] = Y[i];
     }
-    __syncthreads();
+    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+
+    // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
+    //    x held in registers (lane owns rows lane + 64 m), the next reflector
+    //    prefetched while the current one is applied
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double2 *V = a.V + (size_t)plane * F * c;
-    for (int i = t; i < c * F; i += kCoopThreads) {
-        const int vi = i % c, f = i / c;
-        V[(size_t)f * c + vi] = xs[(size_t)vi * F + f];
+    for (int vi = w * kCoopWaves + wave; vi < c; vi += W * kCoopWaves) {
+        const double *y = ts + (size_t)vi * 6 * F + 4 * F;
+        double2 x[kCoopRows], vc[kCoopRows], vn[kCoopRows];
+#pragma unroll
+        for (int m = 0; m < kCoopRows; ++m) {
+            const int q = lane + 64 * m;
+            x[m] = make_double2(q < F ? y[q] : 0.0, 0.0);
+        }
+        auto fetch = [&](int k, double2 *v) {
+#pragma unroll
+            for (int m = 0; m < kCoopRows; ++m) {
+                const int q = lane + 64 * m;
+                v[m] = (q > k && q < F) ? H[(size_t)k * F + q] : make_double2(0.0, 0.0);
+            }
+        };
+        double2 tc = F >= 2 ? tau[F - 2] : make_double2(0.0, 0.0);
+        if (F >= 2) fetch(F - 2, vc);
+        for (int k = F - 2; k >= 0; --k) {
+            double2 tn = make_double2(0.0, 0.0);
+            if (k > 0) {
+                tn = tau[k - 1];
+                fetch(k - 1, vn);
+            }
+            if (tc.x != 0.0 || tc.y != 0.0) {
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int m = 0; m < kCoopRows; ++m) {
+                    const double2 p = cjmul2(vc[m], x[m]);
+                    sr += p.x;
+                    si += p.y;
+                }
+                sr = wsum(sr);
+                si = wsum(si);
+                const double2 s = cmul2(tc, make_double2(sr, si));
+#pragma unroll
+                for (int m = 0; m < kCoopRows; ++m) {
+                    const double2 p = cmul2(vc[m], s);
+                    x[m] = make_double2(x[m].x - p.x, x[m].y - p.y);
+                }
+            }
+            tc = tn;
+#pragma unroll
+            for (int m = 0; m < kCoopRows; ++m) vc[m] = vn[m];
+        }
+#pragma unroll
+        for (int m = 0; m < kCoopRows; ++m) {
+            const int q = lane + 64 * m;
+            if (q < F) V[(size_t)q * c + vi] = x[m];
+        }
     }
 }
 
 int eigen_coop_width(int F) { return std::max(1, std::min(32, cdiv(F, 10))); }
 
-size_t eigen_coop_lds(int F) {
+size_t eigen_coop_lds(int F, int c) {
+    if (F > 64 * kCoopRows) return SIZE_MAX;
     const int W = eigen_coop_width(F);
-    // own columns + 4 vectors; the tail reuses it for d, e^2 and c dots
-    return ((size_t)cdiv(F, W) * F + 4 * (size_t)F) * sizeof(double2) + 64 * sizeof(double);
+    // reduction: own columns + 4 vectors; tail: d, e^2 and either the six LU
+    // arrays or the c Gram-Schmidt vectors plus their dots
+    const size_t red_b = ((size_t)cdiv(F, W) * F + 4 * (size_t)F) * sizeof(double2);
+    const size_t tail_b = (3 * (size_t)F + std::max((size_t)7 * F, (size_t)c * F + c)) * sizeof(double);
+    return std::max(red_b, tail_b) + 64 * sizeof(double);
 }
 
 hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st) {
@@ -478,7 +567,7 @@ hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st) {
     EigArgs a = args;
     void *params[] = {&a};
     return hipLaunchCooperativeKernel((const void *)eigen_coop_kernel, grid, block, params,
-                                      (unsigned)eigen_coop_lds(args.F), st);
+                                      (unsigned)eigen_coop_lds(args.F, args.c), st);
 }
 
 }  // namespace ulm

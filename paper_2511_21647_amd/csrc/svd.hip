@@ -35,7 +35,7 @@ struct EigArgs {
     int F, c, W, planes;
 };
 int eigen_coop_width(int F);
-size_t eigen_coop_lds(int F);
+size_t eigen_coop_lds(int F, int c);
 hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st);
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -688,7 +688,7 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     double *evals = (double *)(ws + w.evals);
-    if (eigen_coop_lds(F) <= 150 * 1024) {
+    if (eigen_coop_lds(F, c) <= 150 * 1024) {
         EigArgs a;
         a.C = C;
         a.H = (double2 *)(ws + w.hvec);

@@ -108,7 +108,8 @@ def train(args):
     sim = Simulator()
     cfg = sim.cfg
     F, nz, nu = cfg.seq.n_frames, cfg.grid.nz, cfg.grid.nu
-    params = torch.from_numpy(init_flat(args.seed)).cuda()
+    init = np.load(args.init).astype(np.float32) if args.init else init_flat(args.seed)
+    params = torch.from_numpy(init).cuda()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     prec = ulm.ULM_CNN_BF16
@@ -119,7 +120,7 @@ def train(args):
     total_steps = args.ensembles * args.passes * (2 * F // B)
     t0 = time.time()
     for i in range(args.ensembles):
-        e = TRAIN_SEED0 + i
+        e = args.first + i
         images, labels, n_mb = sim.ensemble(e)
         losses = []
         for _ in range(args.passes):
@@ -191,9 +192,9 @@ def score(dets, truth, radius=0.5):
             "n_det": n_det, "n_ref": n_ref, "n_match": n_match}
 
 
-def evaluate(weights, ensembles, threshold=0.5, seed0=HELDOUT_SEED0, log_fn=log):
+def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log):
     """NCC and CNN on held-out ensembles: each against the truth, and the CNN
-    against NCC as the judge."""
+    against NCC as the judge, for every CNN decode threshold given."""
     import torch
     import paper_2511_21647_amd as ulm
     sim = Simulator()
@@ -213,12 +214,13 @@ def evaluate(weights, ensembles, threshold=0.5, seed0=HELDOUT_SEED0, log_fn=log)
         ulm.ncc_localize(sim.ctx, sim.proj, cap, locs, count)
         ulm.ulm_check_status(sim.ctx, count, cap)
         ncc = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
-        ulm.ulm_cnn_localize(sim.ctx, params, sim.proj, cap, threshold, 64, ulm.ULM_CNN_BF16,
-                             locs, count, ws=cws)
-        ulm.ulm_check_status(sim.ctx, count, cap)
-        cnn = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
-        r = {"ensemble": e, "n_mb": n_mb, "ncc_vs_truth": score(ncc, truth),
-             "cnn_vs_truth": score(cnn, truth), "cnn_vs_ncc": score(cnn, ncc)}
+        r = {"ensemble": e, "n_mb": n_mb, "ncc_vs_truth": score(ncc, truth), "cnn": {}}
+        for thr in thresholds:
+            ulm.ulm_cnn_localize(sim.ctx, params, sim.proj, cap, thr, 64, ulm.ULM_CNN_BF16,
+                                 locs, count, ws=cws)
+            ulm.ulm_check_status(sim.ctx, count, cap)
+            cnn = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
+            r["cnn"][str(thr)] = {"vs_truth": score(cnn, truth), "vs_ncc": score(cnn, ncc)}
         results.append(r)
         log_fn(json.dumps(r))
     return results
@@ -233,11 +235,15 @@ def main():
     ap.add_argument("--cosine", action="store_true", help="cosine learning-rate decay")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default="cnn_weights.npy")
+    ap.add_argument("--init", default=None, help="weights (.npy) to continue training from")
+    ap.add_argument("--first", type=int, default=TRAIN_SEED0, help="first training ensemble")
     ap.add_argument("--evaluate", default=None, help="weights (.npy) to evaluate instead")
-    ap.add_argument("--threshold", type=float, default=0.5)
+    ap.add_argument("--thresholds", default="0.5",
+                    help="comma-separated CNN decode thresholds to evaluate")
     args = ap.parse_args()
     if args.evaluate:
-        res = evaluate(np.load(args.evaluate), args.ensembles, args.threshold)
+        thr = tuple(float(x) for x in args.thresholds.split(","))
+        res = evaluate(np.load(args.evaluate), args.ensembles, thr)
         with open(os.path.splitext(args.evaluate)[0] + "_eval.json", "w") as fh:
             json.dump(res, fh, indent=1)
     else:

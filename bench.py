@@ -22,6 +22,9 @@ Sub-commands used to produce the committed profiles:
   --profile-das       run the simulator, one stage-1 launch and a 1 GiB copy
                       (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs)
   --summarize-pmc DIR write the counter summary from two rocprofv3 --pmc runs
+  --stream N          streaming run: N consecutive ensembles (MB count ramping
+                      1000 -> 10000, non-rigid tissue motion), both forms per
+                      ensemble, p50/p99 ms and the density-map SSIM of the forms
 """
 from __future__ import annotations
 
@@ -159,6 +162,70 @@ def run_gpu(args):
     return cfg, ms, stage, n, forms
 
 
+def run_stream(args):
+    import numpy as np
+    import torch
+    import paper_2511_21647_amd as ulm
+    from paper_2511_21647_amd.train_cnn import ssim
+    from synth import cfg_stream, make_medium
+
+    N = args.stream
+    cfg0 = cfg_stream(1000)
+    ctx_p = ulm.Context(cfg0)
+    ctx_b = ulm.Context(cfg0, precision=ulm.ULM_PREC_BF16X3)
+    params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()
+    iq = torch.empty(ctx_p.iq_shape, dtype=torch.complex64, device="cuda")
+    proj = torch.empty(ctx_p.proj_shape, dtype=torch.complex64, device="cuda")
+    cap = 4_000_000
+    locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(ctx_b, 64), "cuda")
+    g = cfg0.grid
+    dens = {f: torch.zeros((2, 2 * g.nz, 2 * g.nu), dtype=torch.int32, device="cuda")
+            for f in ("plain", "bf16_cnn")}
+    ms = {"plain": [], "bf16_cnn": []}
+    dets = {"plain": 0, "bf16_cnn": 0}
+    for e in range(N):
+        n_mb = int(round(1000 + 9000 * e / max(N - 1, 1)))
+        cfg = cfg_stream(n_mb)
+        med = make_medium(cfg, e)
+        pos = torch.from_numpy(med.pos).cuda()
+        amp = torch.from_numpy(med.amp).cuda()
+        ulm.ulm_sim_channel_data(ctx_p, pos, amp, med.noise_seed, med.noise_sigma, iq=iq)
+        del pos, amp
+        for form, ctx in (("plain", ctx_p), ("bf16_cnn", ctx_b)):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            ulm.rca_beamform_proj(ctx, iq, proj)
+            ulm.svd_clutter_filter(ctx, proj)
+            if form == "plain":
+                ulm.ncc_localize(ctx, proj, cap, locs, count)
+            else:
+                ulm.ulm_cnn_localize(ctx, params, proj, cap, 0.5, 64, ulm.ULM_CNN_BF16, locs,
+                                     count, ws=cws)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ulm.ulm_check_status(ctx, count, cap)
+            ulm.ulm_density_accumulate(ctx, locs, count, cap, dens[form], upsample=2)
+            ms[form].append(ev[0].elapsed_time(ev[1]))
+            dets[form] += int(count.item())
+        log(f"stream ensemble {e} ({n_mb} MBs): plain {ms['plain'][-1]:.2f} ms, "
+            f"bf16_cnn {ms['bf16_cnn'][-1]:.2f} ms")
+    dp = dens["plain"].cpu().numpy()
+    db = dens["bf16_cnn"].cpu().numpy()
+    out = {"metric": "streaming ms per 300-frame ensemble (p50/p99) and density-map SSIM",
+           "ensembles": N, "acquisition_ms": 750.0,
+           "mb_per_ensemble": [1000, 10000], "motion": "non-rigid, 0.3 mm, 0.5-2 Hz"}
+    for f in ms:
+        a = np.array(ms[f])
+        out[f] = {"p50_ms": round(float(np.percentile(a, 50)), 3),
+                  "p99_ms": round(float(np.percentile(a, 99)), 3),
+                  "max_ms": round(float(a.max()), 3), "detections": dets[f]}
+    out["density_ssim_bf16_cnn_vs_plain"] = [round(ssim(db[o], dp[o]), 4) for o in range(2)]
+    print(json.dumps(out), flush=True)
+
+
 def roofline(cfg, das_ms):
     flops = DAS_FLOPS_PER_EVAL * das_evals(cfg)
     achieved = flops / (das_ms * 1e-3) / 1e12
@@ -277,6 +344,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-das", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--stream", type=int, default=0, metavar="N")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
@@ -288,6 +356,9 @@ def main():
         sys.exit(2)
     if args.profile_das:
         profile_das(args)
+        return
+    if args.stream:
+        run_stream(args)
         return
     cfg, ms_step, stage, n_det, forms = run_gpu(args)
     g = cfg.grid

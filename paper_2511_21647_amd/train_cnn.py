@@ -226,6 +226,21 @@ def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=
     return results
 
 
+def ssim(a, b, sigma=1.5):
+    """Mean structural similarity (Wang et al. 2004) of two maps, Gaussian window
+    (scipy.ndimage), dynamic range of the two maps."""
+    from scipy.ndimage import gaussian_filter
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    L = max(a.max() - a.min(), b.max() - b.min(), 1e-12)
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    g = lambda x: gaussian_filter(x, sigma, mode="reflect", truncate=3.5)
+    ma, mb = g(a), g(b)
+    va, vb, cab = g(a * a) - ma * ma, g(b * b) - mb * mb, g(a * b) - ma * mb
+    return float((((2 * ma * mb + c1) * (2 * cab + c2)) /
+                  ((ma * ma + mb * mb + c1) * (va + vb + c2))).mean())
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--ensembles", type=int, default=48)

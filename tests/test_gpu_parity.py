@@ -271,3 +271,30 @@ def test_density_accumulate(torch, ulm, tiny_cfg):
     ref = pipeline.density_map({"plane": recs["plane"], "z": recs["z"].astype(np.float64),
                                 "u": recs["u"].astype(np.float64)}, 2, g.nz, g.nu)
     assert np.array_equal(dens.cpu().numpy().astype(np.uint32), ref)
+
+
+def test_density_map_ssim(torch, ulm, tiny_cfg):
+    """Density maps accumulated over four tiny ensembles (channel data from the
+    oracle's forward model): the library's whole path and density kernel against
+    the oracle's pipeline and histogram, SSIM per plane."""
+    cfg = tiny_cfg
+    g = cfg.grid
+    ref = np.zeros((2, 2 * g.nz, 2 * g.nu), np.uint32)
+    ctx = ulm.Context(cfg)
+    dens = torch.zeros((2, 2 * g.nz, 2 * g.nu), dtype=torch.int32, device="cuda")
+    n_total = 0
+    for e in range(4):
+        iq = sim.simulate(cfg, make_medium(cfg, e))
+        r = pipeline.reconstruct_ensemble(iq, cfg)
+        ref += pipeline.density_map(r["locs"], 2, g.nz, g.nu)
+        out = ulm.ulm_reconstruct_ensemble(ctx, _to_dev(torch, iq, torch.complex64),
+                                           capacity=100000)
+        ulm.ulm_check_status(ctx, out["count"], 100000)
+        ulm.ulm_density_accumulate(ctx, out["locs"], out["count"], 100000, dens, upsample=2)
+        n_total += int(out["count"].item())
+    got = dens.cpu().numpy().astype(np.uint32)
+    for o in range(2):
+        s = pipeline.ssim(got[o], ref[o])
+        say(f"[density ssim] plane {o}: {got[o].sum()} vs {ref[o].sum()} localisations, SSIM {s:.5f}")
+        assert s >= 0.99
+    assert n_total > 0

@@ -75,7 +75,7 @@ typedef struct ulm_config {
     double  du, dz, u0, z0, dv, v0;
     double  v_ref;        /* stage-1 reference slice position on v           */
     /* clutter filter and localisation */
-    int32_t svd_cutoff;   /* number of removed modes, 0 <= c <= n_frames     */
+    int32_t svd_cutoff;   /* removed modes, 0 <= c <= min(32, n_frames)     */
     int32_t ncc_size;     /* odd template size, 3..15                        */
     int32_t precision;    /* ULM_PREC_*                                      */
     int32_t reserved;

@@ -120,6 +120,7 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.offd = take(sizeof(double) * planes * F);
     w.evals = take(sizeof(double) * planes * F);
     w.evecs = take(sizeof(double2) * planes * F * cc);
+    w.vpad = take(sizeof(double2) * planes * F * removal_cols(c.svd_cutoff));
     w.tscratch = take(sizeof(double) * planes * cc * 6 * F);
     w.xscratch = take(sizeof(double2) * planes * cc * F);
     w.hvec = take(sizeof(double2) * planes * F * F);

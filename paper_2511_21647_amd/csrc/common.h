@@ -61,6 +61,7 @@ struct Workspace {
     size_t offd;        // [planes][F] f64
     size_t evals;       // [planes][F] f64          descending
     size_t evecs;       // [planes][F][c] c128
+    size_t vpad;        // [planes][F][removal_cols(c)] c128, zero past column c
     size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
@@ -79,6 +80,9 @@ struct Workspace {
 };
 
 template <typename T> __host__ __device__ inline T cdiv(T a, T b) { return (a + b - 1) / b; }
+
+// Columns of the padded clutter subspace the removal kernel is compiled for.
+inline int removal_cols(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 24 ? 24 : 32; }
 
 }  // namespace ulm
 

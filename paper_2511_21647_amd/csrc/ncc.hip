@@ -56,6 +56,70 @@ __device__ inline float subpix(float nm, float n0, float np) {
     return fminf(fmaxf(d, -0.5f), 0.5f);
 }
 
+// Peak test, sub-pixel fit and raster-order compaction of one band, from the
+// band's NCC rows (with a halo row above and below) in LDS.
+__device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
+                            const float *__restrict__ fmax_in, ulm_loc_t *__restrict__ staged,
+                            int *__restrict__ band_cnt, const NccParams &prm, int nz, int nu,
+                            int F, int bands, int band_cap, int band, int f, int plane)
+{
+    const int W_out = nu + 2;
+    const int r0 = band * kNccBand;
+    // detection + raster-order compaction within the band
+    __shared__ int wave_tot[4];
+    __shared__ int base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    const float thr_i = prm.alpha * fmax_in[plane * F + f];
+    const int rows = min(kNccBand, nz - r0);
+    const int npx = rows * nu;
+    ulm_loc_t *out = staged + ((size_t)(plane * F + f) * bands + band) * band_cap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e0 = 0; e0 < npx; e0 += blockDim.x) {
+        const int e = e0 + threadIdx.x;
+        bool cand = false;
+        ulm_loc_t rec;
+        if (e < npx) {
+            const int rr = e / nu + 1, cc = e % nu + 1;      // position in the ncc array
+            const float n0 = ncc[rr * W_out + cc];
+            const int z = r0 + rr - 1, u = cc - 1;
+            if (n0 >= prm.tau) {
+                const float2 x = src[(size_t)z * nu + u];
+                const float I = sqrtf(x.x * x.x + x.y * x.y);
+                if (I >= thr_i) {
+                    const float *up = ncc + (rr - 1) * W_out + cc;
+                    const float *mid = ncc + rr * W_out + cc;
+                    const float *dn = ncc + (rr + 1) * W_out + cc;
+                    cand = n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] &&
+                           n0 >= mid[1] && n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
+                    if (cand) {
+                        const float dz = (z > 0 && z < nz - 1) ? subpix(up[0], n0, dn[0]) : 0.f;
+                        const float du = (u > 0 && u < nu - 1) ? subpix(mid[-1], n0, mid[1]) : 0.f;
+                        rec.plane = plane;
+                        rec.frame = f;
+                        rec.iz = z;
+                        rec.iu = u;
+                        rec.z = (float)z + dz;
+                        rec.u = (float)u + du;
+                        rec.ncc = n0;
+                        rec.intensity = I;
+                    }
+                }
+            }
+        }
+        const unsigned long long bal = __ballot(cand);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base_s;
+        for (int q = 0; q < wv; ++q) off += wave_tot[q];
+        if (cand) out[off + pre] = rec;
+        __syncthreads();
+        if (threadIdx.x == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) band_cnt[(plane * F + f) * bands + band] = base_s;
+}
+
 // Dynamic LDS: img [R_in][W_in] (reused for ncc [kNccBand+2][nu+2]), then
 // Vg, V1, V2 [kNccBand+2][W_in].
 __global__ __launch_bounds__(256) void ncc_detect_kernel(
@@ -124,59 +188,92 @@ __global__ __launch_bounds__(256) void ncc_detect_kernel(
     }
     __syncthreads();
 
-    // detection + raster-order compaction within the band
-    __shared__ int wave_tot[4];
-    __shared__ int base_s;
-    if (threadIdx.x == 0) base_s = 0;
-    const float thr_i = prm.alpha * fmax_in[plane * F + f];
-    const int rows = min(kNccBand, nz - r0);
-    const int npx = rows * nu;
-    ulm_loc_t *out = staged + ((size_t)(plane * F + f) * bands + band) * band_cap;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int e0 = 0; e0 < npx; e0 += blockDim.x) {
-        const int e = e0 + threadIdx.x;
-        bool cand = false;
-        ulm_loc_t rec;
-        if (e < npx) {
-            const int rr = e / nu + 1, cc = e % nu + 1;      // position in the ncc array
-            const float n0 = ncc[rr * W_out + cc];
-            const int z = r0 + rr - 1, u = cc - 1;
-            if (n0 >= prm.tau) {
+    detect_band(ncc, src, fmax_in, staged, band_cnt, prm, nz, nu, F, bands, band_cap, band, f,
+                plane);
+}
+
+// Register-column form of the same computation, for images up to 512 - 2 - 2H
+// columns wide: thread t owns input columns t and t + 256 of the band and keeps
+// their 18 + 2H envelope values in registers; each output row's vertical sums go
+// through a small double-buffered LDS row, and the NCC rows of the band stay in
+// LDS for the peak test.  About 27 KB of LDS per work-group at the paper's width
+// (against ~91 KB for the staged form), so five work-groups share a CU.
+template <int H>
+__global__ __launch_bounds__(256) void ncc_band_kernel(
+    const float2 *__restrict__ P, const float *__restrict__ fmax_in, ulm_loc_t *__restrict__ staged,
+    int *__restrict__ band_cnt, NccParams prm, int nz, int nu, int F, int bands, int band_cap)
+{
+    constexpr int S = 2 * H + 1;
+    constexpr int R_out = kNccBand + 2;
+    constexpr int R_in = R_out + 2 * H;
+    extern __shared__ float smem[];
+    const int band = blockIdx.x, f = blockIdx.y, plane = blockIdx.z;
+    const int W_in = nu + 2 + 2 * H, W_out = nu + 2;
+    float *V = smem;                                // [2][3][W_in]
+    float *ncc = smem + 6 * W_in;                   // [R_out][W_out]
+    const int t = threadIdx.x;
+    const int r0 = band * kNccBand;
+    const float2 *src = P + ((size_t)plane * F + f) * (size_t)nz * nu;
+
+    float col[2][R_in];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int cc = t + 256 * q, u = cc - 1 - H;
+        const bool cu = cc < W_in && u >= 0 && u < nu;
+#pragma unroll
+        for (int rr = 0; rr < R_in; ++rr) {
+            const int z = r0 - 1 - H + rr;
+            float v = 0.f;
+            if (cu && z >= 0 && z < nz) {
                 const float2 x = src[(size_t)z * nu + u];
-                const float I = sqrtf(x.x * x.x + x.y * x.y);
-                if (I >= thr_i) {
-                    const float *up = ncc + (rr - 1) * W_out + cc;
-                    const float *mid = ncc + rr * W_out + cc;
-                    const float *dn = ncc + (rr + 1) * W_out + cc;
-                    cand = n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] &&
-                           n0 >= mid[1] && n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
-                    if (cand) {
-                        const float dz = (z > 0 && z < nz - 1) ? subpix(up[0], n0, dn[0]) : 0.f;
-                        const float du = (u > 0 && u < nu - 1) ? subpix(mid[-1], n0, mid[1]) : 0.f;
-                        rec.plane = plane;
-                        rec.frame = f;
-                        rec.iz = z;
-                        rec.iu = u;
-                        rec.z = (float)z + dz;
-                        rec.u = (float)u + du;
-                        rec.ncc = n0;
-                        rec.intensity = I;
-                    }
+                v = sqrtf(x.x * x.x + x.y * x.y);
+            }
+            col[q][rr] = v;
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < R_out; ++rr) {
+        float *Vb = V + (rr & 1) * 3 * W_in;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int cc = t + 256 * q;
+            if (cc < W_in) {
+                float sg = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+                for (int a = 0; a < S; ++a) {
+                    const float x = col[q][rr + a];
+                    sg = fmaf(prm.gz[a], x, sg);
+                    s1 += x;
+                    s2 = fmaf(x, x, s2);
                 }
+                Vb[cc] = sg;
+                Vb[W_in + cc] = s1;
+                Vb[2 * W_in + cc] = s2;
             }
         }
-        const unsigned long long bal = __ballot(cand);
-        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_tot[wv] = __popcll(bal);
         __syncthreads();
-        int off = base_s;
-        for (int q = 0; q < wv; ++q) off += wave_tot[q];
-        if (cand) out[off + pre] = rec;
-        __syncthreads();
-        if (threadIdx.x == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-        __syncthreads();
+        const int z = r0 - 1 + rr;
+        for (int co = t; co < W_out; co += 256) {
+            const int u = co - 1;
+            float out = -INFINITY;                  // outside the image: ignored by the peak test
+            if (z >= 0 && z < nz && u >= 0 && u < nu) {
+                float sik = 0.f, si = 0.f, si2 = 0.f;
+#pragma unroll
+                for (int b = 0; b < S; ++b) {
+                    sik = fmaf(prm.gu[b], Vb[co + b], sik);
+                    si += Vb[W_in + co + b];
+                    si2 += Vb[2 * W_in + co + b];
+                }
+                const float num = sik - prm.kbar * si;
+                const float var = si2 - si * si * prm.inv_w;
+                out = var > 1e-6f * si2 ? num * prm.inv_sk * rsqrtf(var) : 0.f;
+            }
+            ncc[rr * W_out + co] = out;
+        }
     }
-    if (threadIdx.x == 0) band_cnt[(plane * F + f) * bands + band] = base_s;
+    __syncthreads();
+    detect_band(ncc, src, fmax_in, staged, band_cnt, prm, nz, nu, F, bands, band_cap, band, f,
+                plane);
 }
 
 // Exclusive scan of n counts by one work-group; writes the total to *count.
@@ -284,9 +381,31 @@ hipError_t launch_localize(const ulm_ctx *ctx, const float2 *filt, ulm_loc_t *lo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const NccParams prm = make_ncc_params(ctx);
-    const size_t lds = ncc_lds_bytes(g.nu, prm.half);
-    hipLaunchKernelGGL(ncc_detect_kernel, dim3(w.bands, F, planes), dim3(256), lds, st, filt, fmx,
-                       staged, bcnt, prm, g.nz, g.nu, F, w.bands, w.band_cap);
+    const dim3 grid(w.bands, F, planes);
+    const int W_in = g.nu + 2 + 2 * prm.half;
+    if (W_in <= 512) {
+        const size_t lds = (6 * (size_t)W_in + (size_t)(kNccBand + 2) * (g.nu + 2)) * sizeof(float);
+#define ULM_NCC_BAND(HH)                                                                          \
+    case HH:                                                                                      \
+        hipLaunchKernelGGL(ncc_band_kernel<HH>, grid, dim3(256), lds, st, filt, fmx, staged, bcnt, \
+                           prm, g.nz, g.nu, F, w.bands, w.band_cap);                              \
+        break;
+        switch (prm.half) {
+            ULM_NCC_BAND(1)
+            ULM_NCC_BAND(2)
+            ULM_NCC_BAND(3)
+            ULM_NCC_BAND(4)
+            ULM_NCC_BAND(5)
+            ULM_NCC_BAND(6)
+            ULM_NCC_BAND(7)
+            default: return hipErrorInvalidValue;
+        }
+#undef ULM_NCC_BAND
+    } else {
+        const size_t lds = ncc_lds_bytes(g.nu, prm.half);
+        hipLaunchKernelGGL(ncc_detect_kernel, grid, dim3(256), lds, st, filt, fmx, staged, bcnt,
+                           prm, g.nz, g.nu, F, w.bands, w.band_cap);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int nslots = planes * F * w.bands;
     hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(1024), 0, st, bcnt, boff, nslots, count);

@@ -617,43 +617,54 @@ __global__ void clear_status_kernel(int *status, int *bar, int *eflag, int plane
 }
 
 // ---------------------------------------------------------------- removal
-// I_f = I - (I V_c) V_c^H per pixel time series, accumulated in FP64.
+// The clutter eigenvectors copied to CM columns, zero past column c, so the
+// removal runs branch-free with compile-time strides (a zero column adds
+// exact zeros).
+__global__ void pad_subspace_kernel(const double2 *__restrict__ V, double2 *__restrict__ Vp, int F,
+                                    int c, int CM, int planes)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= planes * F * CM) return;
+    const int col = i % CM, row = i / CM;              // row = plane * F + f
+    Vp[i] = col < c ? V[(size_t)row * c + col] : make_double2(0.0, 0.0);
+}
+
+// I_f = I - (I V_c) V_c^H per pixel time series, accumulated in FP64; one
+// thread per pixel, V (uniform across the wave) read through the scalar cache.
 template <int CM>
 __global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
                                                       const double2 *__restrict__ V, int F,
-                                                      int npix, int c, const int *__restrict__ eflag)
+                                                      int npix, const int *__restrict__ eflag)
 {
     const int plane = blockIdx.y;
     if (eflag[plane]) return;      // non-finite covariance: the plane stays unfiltered
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     float2 *col = P + (size_t)plane * F * npix + p;
-    const double2 *Vp = V + (size_t)plane * F * c;
+    const double2 *Vp = V + (size_t)plane * F * CM;
     double2 y[CM];
 #pragma unroll
     for (int i = 0; i < CM; ++i) y[i] = make_double2(0.0, 0.0);
     for (int g = 0; g < F; ++g) {
         const float2 xf = col[(size_t)g * npix];
         const double xr = xf.x, xi = xf.y;
+        const double2 *vg = Vp + (size_t)g * CM;
 #pragma unroll
         for (int i = 0; i < CM; ++i) {
-            if (i < c) {
-                const double2 v = Vp[g * c + i];
-                y[i].x = fma(xr, v.x, fma(-xi, v.y, y[i].x));
-                y[i].y = fma(xr, v.y, fma(xi, v.x, y[i].y));
-            }
+            const double2 v = vg[i];
+            y[i].x = fma(xr, v.x, fma(-xi, v.y, y[i].x));
+            y[i].y = fma(xr, v.y, fma(xi, v.x, y[i].y));
         }
     }
     for (int f = 0; f < F; ++f) {
         const float2 xf = col[(size_t)f * npix];
+        const double2 *vf = Vp + (size_t)f * CM;
         double rr = 0.0, ri = 0.0;
 #pragma unroll
         for (int i = 0; i < CM; ++i) {
-            if (i < c) {
-                const double2 v = Vp[f * c + i];   // y * conj(v)
-                rr = fma(y[i].x, v.x, fma(y[i].y, v.y, rr));
-                ri = fma(y[i].y, v.x, fma(-y[i].x, v.y, ri));
-            }
+            const double2 v = vf[i];                   // y * conj(v)
+            rr = fma(y[i].x, v.x, fma(y[i].y, v.y, rr));
+            ri = fma(y[i].y, v.x, fma(-y[i].x, v.y, ri));
         }
         col[(size_t)f * npix] = make_float2((float)((double)xf.x - rr), (float)((double)xf.y - ri));
     }
@@ -720,19 +731,19 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (c > 0) {
+        const int CM = removal_cols(c);
+        double2 *Vp = (double2 *)(ws + w.vpad);
+        hipLaunchKernelGGL(pad_subspace_kernel, dim3(cdiv(planes * F * CM, 256)), dim3(256), 0, st,
+                           (const double2 *)(ws + w.evecs), Vp, F, c, CM, planes);
         dim3 grid(cdiv(npix, 256), planes);
-        const double2 *V = (const double2 *)(ws + w.evecs);
         const int *eflag = (const int *)(ws + w.eflag);
-        if (c <= 4)
-            hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
-        else if (c <= 8)
-            hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
-        else if (c <= 16)
-            hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
-        else if (c <= 24)
-            hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
-        else
-            hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, V, F, npix, c, eflag);
+        switch (CM) {
+            case 4: hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            case 8: hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            case 16: hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            case 24: hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            default: hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

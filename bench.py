@@ -109,7 +109,7 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
         if form == "plain":
             ulm.ncc_localize(ctx, proj, cap, locs, count)
         else:
-            ulm.ulm_cnn_localize(ctx, cnn_params, proj, cap, 0.5, 64, ulm.ULM_CNN_BF16, locs,
+            ulm.ulm_cnn_localize(ctx, cnn_params, proj, cap, ulm.CNN_THRESHOLD, 64, ulm.ULM_CNN_BF16, locs,
                                  count, ws=cws)
         if ev: ev[4].record()
 
@@ -202,7 +202,7 @@ def run_stream(args):
             if form == "plain":
                 ulm.ncc_localize(ctx, proj, cap, locs, count)
             else:
-                ulm.ulm_cnn_localize(ctx, params, proj, cap, 0.5, 64, ulm.ULM_CNN_BF16, locs,
+                ulm.ulm_cnn_localize(ctx, params, proj, cap, ulm.CNN_THRESHOLD, 64, ulm.ULM_CNN_BF16, locs,
                                      count, ws=cws)
             ev[1].record()
             torch.cuda.synchronize()

@@ -28,6 +28,9 @@ ULM_CNN_PARAMS = 48672
 ULM_CNN_BF16 = 0
 ULM_CNN_FP32 = 1
 CNN_UPSAMPLE = 8
+# heat threshold of the trained network's peak decode (best F1 against the truth
+# among the thresholds swept on held-out simulated ensembles)
+CNN_THRESHOLD = 0.1
 # order and shapes of the CNN's flat FP32 parameter vector
 CNN_LAYOUT = ([("w0", (32, 1, 3, 3)), ("b0", (32,))]
               + [item for l in range(1, 6) for item in ((f"w{l}", (32, 32, 3, 3)), (f"b{l}", (32,)))]
@@ -485,7 +488,7 @@ def ulm_cnn_train_step(params, adam_m, adam_v, step: int, lr: float, images, mb_
     return loss
 
 
-def ulm_cnn_localize(ctx: Context, params, filtered, capacity: int, threshold: float = 0.5,
+def ulm_cnn_localize(ctx: Context, params, filtered, capacity: int, threshold: float = CNN_THRESHOLD,
                      batch: int = 64, precision: int = ULM_CNN_BF16, locs=None, count=None,
                      ws=None, stream=None):
     """CNN localisation of the filtered planes; returns (locs, count) as ncc_localize."""

@@ -118,88 +118,131 @@ __global__ __launch_bounds__(256) void cnn_conv0_kernel(const float *__restrict_
             in[dy * 3 + dx] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
                                   ? x0[(n * H + yy) * W + xx] : 0.f;
         }
-    T *dst = a1 + idx * kC;
-#pragma unroll 4
+    // 32 outputs of this pixel, written as 16-byte vectors
+    T res[kC];
+#pragma unroll
     for (int o = 0; o < kC; ++o) {
         float s = 0.f;
 #pragma unroll
         for (int t = 0; t < 9; ++t) s = fmaf(w[o * 9 + t], in[t], s);
-        dst[o] = fromf<T>(fmaxf(s + w[kW0 + o], 0.f));
+        res[o] = fromf<T>(fmaxf(s + w[kW0 + o], 0.f));
     }
+    uint4 *dst = reinterpret_cast<uint4 *>(a1 + idx * kC);
+#pragma unroll
+    for (int q = 0; q < (int)(kC * sizeof(T) / 16); ++q) dst[q] = reinterpret_cast<const uint4 *>(res)[q];
 }
 
 // ----------------------------------------------------------------- 32 -> 32 conv
 // out[n][y][x][o] = epi( sum_{tap, c} w[o][tap][c] in[n][y + dy - 1][x + dx - 1][c] )
 // MASK = false: + bias, ReLU (forward).  MASK = true: zero where mask <= 0 (data gradient).
+// Persistent: each work-group stages the layer's weights in LDS once and then
+// walks the 4 x 32 pixel tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
+// results go through a per-wave LDS transpose so every lane writes whole
+// 16-byte channel groups.
+template <typename T>
+constexpr int kEpiStride = kC + 16 / (int)sizeof(T);     // padded channels per staged pixel
+
 template <typename T, bool MASK>
 __global__ __launch_bounds__(256) void cnn_conv_kernel(const T *__restrict__ in,
                                                        const T *__restrict__ w,
                                                        const float *__restrict__ bias,
                                                        const T *__restrict__ mask,
-                                                       T *__restrict__ out, int H, int W)
+                                                       T *__restrict__ out, int H, int W, int B)
 {
-    constexpr int PS = Lds<T>::px, WS = Lds<T>::w, TC = kTileCols + 2;
+    constexpr int PS = Lds<T>::px, WS = Lds<T>::w, TC = kTileCols + 2, ES = kEpiStride<T>;
+    constexpr int VEC = 16 / (int)sizeof(T);                // elements per 16-byte vector
     __shared__ __attribute__((aligned(16))) T tile[(kTileRows + 2) * TC * PS];
     __shared__ __attribute__((aligned(16))) T wl[kC * WS];
-    const int n = blockIdx.z, y0 = blockIdx.y * kTileRows, x0 = blockIdx.x * kTileCols;
+    static_assert(4 * kTileCols * ES <= (kTileRows + 2) * TC * PS, "epilogue fits in the tile");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     if constexpr (sizeof(T) == 2) {
         for (int e = t; e < kC * 36; e += 256) {
             const int o = e / 36, q = e % 36;
             *reinterpret_cast<uint4 *>(&wl[o * WS + q * 8]) = reinterpret_cast<const uint4 *>(w)[e];
         }
-        for (int e = t; e < (kTileRows + 2) * TC * 4; e += 256) {
-            const int q = e & 3, px = (e >> 2) % TC, ry = (e >> 2) / TC;
-            const int yy = y0 + ry - 1, xx = x0 + px - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                v = reinterpret_cast<const uint4 *>(in + (((size_t)n * H + yy) * W + xx) * kC)[q];
-            *reinterpret_cast<uint4 *>(&tile[(ry * TC + px) * PS + q * 8]) = v;
-        }
     } else {
         for (int e = t; e < kC * 9 * kC; e += 256) wl[(e / (9 * kC)) * WS + e % (9 * kC)] = w[e];
-        for (int e = t; e < (kTileRows + 2) * TC * kC; e += 256) {
-            const int c = e % kC, px = (e / kC) % TC, ry = e / (kC * TC);
-            const int yy = y0 + ry - 1, xx = x0 + px - 1;
-            tile[(ry * TC + px) * PS + c] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                                                ? in[(((size_t)n * H + yy) * W + xx) * kC + c] : 0.f;
-        }
     }
-    __syncthreads();
+    const int tx = cdiv(W, kTileCols), ty = cdiv(H, kTileRows);
+    const long ntiles = (long)tx * ty * B;
     const int i32 = lane & 31, hk = lane >> 5;
-    f32x16 acc = {};
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap % 3;
-        const T *arow = &tile[((wave + dy) * TC + i32 + dx) * PS];
-        const T *brow = &wl[i32 * WS + tap * kC];
+    const float b = MASK ? 0.f : bias[i32];
+    for (long tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const int n = (int)(tl / ((long)tx * ty)), y0 = (int)((tl / tx) % ty) * kTileRows,
+                  x0 = (int)(tl % tx) * kTileCols;
+        __syncthreads();       // the previous tile's readers are done with `tile`
         if constexpr (sizeof(T) == 2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(arow + h * 16 + hk * 8);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(brow + h * 16 + hk * 8);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            for (int e = t; e < (kTileRows + 2) * TC * 4; e += 256) {
+                const int q = e & 3, px = (e >> 2) % TC, ry = (e >> 2) / TC;
+                const int yy = y0 + ry - 1, xx = x0 + px - 1;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = reinterpret_cast<const uint4 *>(in + (((size_t)n * H + yy) * W + xx) * kC)[q];
+                *reinterpret_cast<uint4 *>(&tile[(ry * TC + px) * PS + q * 8]) = v;
             }
         } else {
-#pragma unroll
-            for (int s = 0; s < 16; ++s)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * s + hk], brow[2 * s + hk], acc, 0, 0, 0);
+            for (int e = t; e < (kTileRows + 2) * TC * kC; e += 256) {
+                const int c = e % kC, px = (e / kC) % TC, ry = e / (kC * TC);
+                const int yy = y0 + ry - 1, xx = x0 + px - 1;
+                tile[(ry * TC + px) * PS + c] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                                                    ? in[(((size_t)n * H + yy) * W + xx) * kC + c] : 0.f;
+            }
         }
-    }
-    const int y = y0 + wave;
-    if (y >= H) return;
-    // lane holds D[8 (q / 4) + 4 hk + q % 4][i32]: pixel x0 + that row, output channel i32
-    const int o = i32;
-    const float b = MASK ? 0.f : bias[o];
+        __syncthreads();
+        f32x16 acc = {};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int x = x0 + 8 * (q >> 2) + 4 * hk + (q & 3);
-        if (x >= W) continue;
-        const size_t at = (((size_t)n * H + y) * W + x) * kC + o;
-        float v = acc[q];
-        if constexpr (MASK) v = tof(mask[at]) > 0.f ? v : 0.f;
-        else v = fmaxf(v + b, 0.f);
-        out[at] = fromf<T>(v);
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            const T *arow = &tile[((wave + dy) * TC + i32 + dx) * PS];
+            const T *brow = &wl[i32 * WS + tap * kC];
+            if constexpr (sizeof(T) == 2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(arow + h * 16 + hk * 8);
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(brow + h * 16 + hk * 8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int s2 = 0; s2 < 16; ++s2)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * s2 + hk], brow[2 * s2 + hk],
+                                                               acc, 0, 0, 0);
+            }
+        }
+        // lane holds D[8 (q / 4) + 4 hk + q % 4][i32]: pixel row of the tile, output channel i32;
+        // the tile's LDS is reused to transpose the results (every wave is done reading it)
+        __syncthreads();
+        T *epw = tile + wave * kTileCols * ES;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int pr = 8 * (q >> 2) + 4 * hk + (q & 3);
+            const float v = MASK ? acc[q] : fmaxf(acc[q] + b, 0.f);
+            epw[pr * ES + i32] = fromf<T>(v);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);       // this wave's LDS writes have landed
+        __builtin_amdgcn_wave_barrier();
+        const int y = y0 + wave;
+        if (y < H) {
+            constexpr int NV = kTileCols * kC / VEC;     // 16-byte vectors per wave row
+#pragma unroll
+            for (int c = lane; c < NV; c += 64) {
+                const int pr = c / (kC / VEC), g = c % (kC / VEC);
+                const int x = x0 + pr;
+                if (x < W) {
+                    const size_t at = (((size_t)n * H + y) * W + x) * kC + g * VEC;
+                    uint4 v = *reinterpret_cast<const uint4 *>(&epw[pr * ES + g * VEC]);
+                    if constexpr (MASK) {
+                        const uint4 mv = *reinterpret_cast<const uint4 *>(mask + at);
+                        const T *mk = reinterpret_cast<const T *>(&mv);
+                        T *vv = reinterpret_cast<T *>(&v);
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i)
+                            if (!(tof(mk[i]) > 0.f)) vv[i] = fromf<T>(0.f);
+                    }
+                    *reinterpret_cast<uint4 *>(out + at) = v;
+                }
+            }
+        }
     }
 }
 
@@ -333,46 +376,63 @@ __global__ __launch_bounds__(256) void cnn_head_decode_kernel(
             }
         }
         __syncthreads();
-        // decode the 32 x 64 fine pixels of row y in this chunk
-        for (int e0 = 0; e0 < kTileCols * kR2; e0 += 256) {
-            const int e = e0 + t;
-            const int cx = e / kR2, i = (e % kR2) / kR, j = e % kR;
-            const int x = x0 + cx;
-            bool cand = false;
-            float v = 0.f;
-            if (x < W) {
-                v = hs[1][1 + cx][i * kR + j];
+        // decode the 32 x 64 fine pixels of row y in this chunk: thread t tests the
+        // 8 fine pixels (coarse column t / 8, fine row t % 8), so thread order is
+        // the raster order of the chunk; a wave scan and the wave totals give
+        // every candidate its slot
+        const int cx = t >> 3, i = t & 7, x = x0 + cx;
+        unsigned bits = 0;
+        float vals[kR];
+        if (x < W) {
+#pragma unroll
+            for (int j = 0; j < kR; ++j) {
+                const float v = hs[1][1 + cx][i * kR + j];
+                vals[j] = v;
                 auto nb8 = [&](int dz, int du) {
                     const int fi = 8 + i + dz, fj = 8 + j + du;      // fine offsets within rows y-1..y+1
                     return hs[fi >> 3][cx + (fj >> 3)][(fi & 7) * kR + (fj & 7)];
                 };
-                cand = v >= thr && v > nb8(-1, -1) && v > nb8(-1, 0) && v > nb8(-1, 1) &&
-                       v > nb8(0, -1) && v >= nb8(0, 1) && v >= nb8(1, -1) && v >= nb8(1, 0) &&
-                       v >= nb8(1, 1);
+                const bool cand = v >= thr && v > nb8(-1, -1) && v > nb8(-1, 0) &&
+                                  v > nb8(-1, 1) && v > nb8(0, -1) && v >= nb8(0, 1) &&
+                                  v >= nb8(1, -1) && v >= nb8(1, 0) && v >= nb8(1, 1);
+                bits |= cand ? 1u << j : 0u;
             }
-            const unsigned long long bal = __ballot(cand);
-            if (lane == 0) wave_tot[wave] = __popcll(bal);
-            __syncthreads();
-            int off = base_s;
-            for (int q = 0; q < wave; ++q) off += wave_tot[q];
-            off += __popcll(bal & ((1ull << lane) - 1ull));
-            if (cand && off < row_cap) {
-                ulm_loc_t rec;
-                rec.plane = img / F;
-                rec.frame = img % F;
-                rec.iz = y;
-                rec.iu = x;
-                rec.z = ((float)(y * kR + i) + 0.5f) / kR - 0.5f;
-                rec.u = ((float)(x * kR + j) + 0.5f) / kR - 0.5f;
-                rec.ncc = v;
-                const float2 pv = P[((size_t)img * H + y) * W + x];
-                rec.intensity = sqrtf(pv.x * pv.x + pv.y * pv.y);
-                out[off] = rec;
-            }
-            __syncthreads();
-            if (t == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-            __syncthreads();
         }
+        const int cnt = __popc(bits);
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) wave_tot[wave] = incl;
+        __syncthreads();
+        int off = base_s + incl - cnt;
+        for (int q = 0; q < wave; ++q) off += wave_tot[q];
+        if (bits) {
+            const float2 pv = P[((size_t)img * H + y) * W + x];
+            const float inten = sqrtf(pv.x * pv.x + pv.y * pv.y);
+#pragma unroll
+            for (int j = 0; j < kR; ++j) {
+                if (!(bits & (1u << j))) continue;
+                if (off < row_cap) {
+                    ulm_loc_t rec;
+                    rec.plane = img / F;
+                    rec.frame = img % F;
+                    rec.iz = y;
+                    rec.iu = x;
+                    rec.z = ((float)(y * kR + i) + 0.5f) / kR - 0.5f;
+                    rec.u = ((float)(x * kR + j) + 0.5f) / kR - 0.5f;
+                    rec.ncc = vals[j];
+                    rec.intensity = inten;
+                    out[off] = rec;
+                }
+                ++off;
+            }
+        }
+        __syncthreads();       // hs and wave_tot are rewritten by the next chunk
+        if (t == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
     }
     if (t == 0) {
         row_cnt[(size_t)img * H + y] = min(base_s, row_cap);
@@ -696,6 +756,12 @@ size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32) {
     return cnn_loc_layout(batch, H, W, n_img, fp32).total;
 }
 
+// Persistent conv grid: enough work-groups to fill every CU a few times over.
+static unsigned conv_grid(int B, int H, int W) {
+    const long tiles = (long)cdiv(W, kTileCols) * cdiv(H, kTileRows) * B;
+    return (unsigned)std::min(tiles, 256L * 8);
+}
+
 template <typename T>
 static hipError_t run_forward(const float *params, const float *x0, T *const *act, int n_act,
                               T *wm, T *wt, int B, int H, int W, hipStream_t st, int *last)
@@ -705,13 +771,13 @@ static hipError_t run_forward(const float *params, const float *x0, T *const *ac
                        params, wm, wt);
     hipLaunchKernelGGL(cnn_conv0_kernel<T>, dim3((unsigned)cdiv(npx, (size_t)256)), dim3(256), 0, st,
                        x0, params, act[0], H, W, npx);
-    const dim3 grid(cdiv(W, kTileCols), cdiv(H, kTileRows), B);
+    const dim3 grid(conv_grid(B, H, W));
     int cur = 0;
     for (int l = 1; l < kL; ++l) {
         const int nxt = n_act == kL ? l : cur ^ 1;
         hipLaunchKernelGGL((cnn_conv_kernel<T, false>), grid, dim3(256), 0, st, act[cur],
                            wm + (size_t)(l - 1) * kWl, params + off_b(l), (const T *)nullptr,
-                           act[nxt], H, W);
+                           act[nxt], H, W, B);
         cur = nxt;
     }
     *last = cur;
@@ -793,9 +859,9 @@ static hipError_t gradients_t(const float *params, const float *x0, const float 
                            dz[cur], part, H, W, B);
         hipLaunchKernelGGL(cnn_reduce_kernel, dim3(cdiv(kWl + kBl, 256)), dim3(256), 0, st, part, gw,
                            kWl + kBl, grad, off_w(l));
-        hipLaunchKernelGGL((cnn_conv_kernel<T, true>), grid, dim3(256), 0, st, dz[cur],
-                           wt + (size_t)(l - 1) * kWl, (const float *)nullptr, act[l - 1],
-                           dz[cur ^ 1], H, W);
+        hipLaunchKernelGGL((cnn_conv_kernel<T, true>), dim3(conv_grid(B, H, W)), dim3(256), 0, st,
+                           dz[cur], wt + (size_t)(l - 1) * kWl, (const float *)nullptr,
+                           act[l - 1], dz[cur ^ 1], H, W, B);
         cur ^= 1;
     }
     hipLaunchKernelGGL(cnn_conv0_bwd_weight_kernel<T>, dim3(gw), dim3(kW0 + kB0), 0, st, x0, dz[cur],

@@ -10,8 +10,9 @@
 //      k-1 is applied lazily, fused with the matrix-vector product of step k,
 //      and every work-group forms the reflector v_k itself from the published
 //      column k, so each step costs one grid barrier: after every work-group
-//      has published its part of p_k = tau_k A v_k and its share of p^H v, and
-//      the owner of column k+1 has published that column.
+//      has published its part of p_k = tau_k A v_k and the owner of column k+1
+//      has published that column; every work-group then reads all of p and
+//      forms p^H v itself.
 //   2. Every eigenvalue of T by multisection on Sturm counts (a wave per
 //      eigenvalue, 64 points per round), spread over the plane's work-groups.
 //   3. Inverse iteration (partial-pivoting tridiagonal LU in LDS) for the c
@@ -44,7 +45,7 @@ struct EigArgs {
     double2 *xscr;      // [planes][c][F]
     double2 *vbuf;      // [planes][F] reflector of the current step
     double2 *pbuf;      // [planes][F]
-    double *dots;       // [planes][W][2]
+    double *dots;       // unused
     double *scal;       // unused
     int *bar;           // [planes] barrier counters, zero at launch
     int *flag;          // [planes] non-finite input
@@ -69,6 +70,19 @@ __device__ inline double bsum(double v, double *red) {
     __syncthreads();
     double s = 0.0;
     for (int i = 0; i < kCoopWaves; ++i) s += red[i];
+    return s;
+}
+__device__ inline double2 bsum2(double a, double b, double2 *red) {
+    a = wsum(a);
+    b = wsum(b);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(a, b);
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < kCoopWaves; ++i) {
+        s.x += red[i].x;
+        s.y += red[i].y;
+    }
     return s;
 }
 __device__ inline double bmax(double v, double *red) {
@@ -186,10 +200,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     double2 *H = a.H + (size_t)plane * F * F;
     double2 *tau = a.tau + (size_t)plane * F;
     double *d = a.d + (size_t)plane * F, *e = a.e + (size_t)plane * F;
-    // double-buffered exchange areas (by step parity): p, the next column, dots
+    // double-buffered exchange areas (by step parity): p and the next column
     double2 *pbuf = a.pbuf + (size_t)plane * 2 * F;
     double2 *cbuf = a.vbuf + (size_t)plane * 2 * F;
-    double *dots = a.dots + (size_t)plane * 2 * 64;
     int *cnt = a.bar + plane;
     int nbar = 0;
 
@@ -251,7 +264,6 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             }
         }
         // own columns j > k: pending update, then p_j = tau_k sum_i conj(A[i][j]) v_i
-        double2 part = make_double2(0.0, 0.0);
         for (int q = wave; q < ncol; q += kCoopWaves) {
             const int j = w + q * W;
             if (j <= k || j >= F) continue;
@@ -272,36 +284,29 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             ai = wsum(ai);
             const double2 pj = cmul2(tk, make_double2(ar, ai));
             if (lane == 0) st_c2(pbuf + par * F + j, pj);
-            const double2 pv = cjmul2(pj, svn[j]);
-            part.x += pv.x;
-            part.y += pv.y;
             if (j == k + 1)    // publish the next column (rows > k) for every work-group
                 for (int i = k + 1 + lane; i < F; i += 64) st_c2(cbuf + par * F + i, col[i]);
         }
-        if (lane == 0) wpart[wave] = part;
-        __syncthreads();
-        if (t == 0) {
-            double2 s = make_double2(0.0, 0.0);
-            for (int q = 0; q < kCoopWaves; ++q) { s.x += wpart[q].x; s.y += wpart[q].y; }
-            st_c(dots + par * 64 + 2 * w, s.x);
-            st_c(dots + par * 64 + 2 * w + 1, s.y);
-        }
         if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
-        // the W partial dots: one load per lane (re on even lanes, im on odd), one reduction
-        const double dl = lane < 2 * W ? ld_c(dots + par * 64 + lane) : 0.0;
-        const double pr = wsum((lane & 1) ? 0.0 : dl), pi = wsum((lane & 1) ? dl : 0.0);
-        // alpha = -1/2 tau (p^H v); the pending update uses 2 Re(alpha)
-        const double2 al = cmul2(make_double2(-0.5 * tk.x, -0.5 * tk.y), make_double2(pr, pi));
-        a2r = 2.0 * al.x;
+        // every work-group reads all of p and the next column, and forms p^H v itself
+        double ppr = 0.0, ppi = 0.0;
         for (int i = t; i < F; i += kCoopThreads) {
             // both loads issued before either is used (rows <= k read a valid, unused slot)
             const int ii = i > k ? i : F - 1;
             const double2 pv = ld_c2(pbuf + par * F + ii), cv = ld_c2(cbuf + par * F + ii);
+            if (i > k) {
+                const double2 dv = cjmul2(pv, svn[i]);
+                ppr += dv.x;
+                ppi += dv.y;
+            }
             sv[i] = i > k ? svn[i] : make_double2(0.0, 0.0);
             sp[i] = i > k ? pv : make_double2(0.0, 0.0);
             if (i > k) scol[i] = cv;
         }
-        __syncthreads();
+        const double2 pvh = bsum2(ppr, ppi, wpart);     // its syncs also publish sp, sv, scol
+        // alpha = -1/2 tau (p^H v); the pending update uses 2 Re(alpha)
+        const double2 al = cmul2(make_double2(-0.5 * tk.x, -0.5 * tk.y), pvh);
+        a2r = 2.0 * al.x;
     }
     // last diagonal entry: pending update of step F-2 applied to A[F-1][F-1]
     if (w == 0 && t == 0) {

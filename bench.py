@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 DAS_FLOPS_PER_EVAL = 14        # complex lerp (2 sub + 2 FMA = 6) + complex multiply-add (8)
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "das_stage1_paper_counters.json")
-DAS_SOURCE = os.path.join(ROOT, "paper_2511_21647_amd", "csrc", "beamform.hip")
+DAS_SOURCE = os.path.join(ROOT, "paper_2511_21647_amd", "csrc", "das.hip")
 COPY_BYTES = 1 << 30
 
 

@@ -95,6 +95,14 @@ typedef struct ulm_loc {
     float   intensity;    /* envelope at the peak                            */
 } ulm_loc_t;
 
+/* A 3D localisation paired from one XZ and one YZ localisation of a frame. */
+typedef struct ulm_loc3d {
+    int32_t frame;
+    float   x, y, z;          /* plane pixel units: x of the XZ record, y of the YZ record, mean z */
+    float   i_xz, i_yz;       /* the two records' intensities                      */
+    int32_t idx_xz, idx_yz;   /* their indices in the input list                   */
+} ulm_loc3d_t;
+
 typedef struct ulm_timing {
     float ms_beamform, ms_filter, ms_localize, ms_total;
 } ulm_timing_t;
@@ -217,6 +225,30 @@ int32_t ulm_sim_channel_data(ulm_ctx_t *ctx, const double *pos, const double *am
 int32_t ulm_density_accumulate(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
                                int32_t capacity, int32_t upsample, uint32_t *density,
                                void *stream);
+
+/* Workspace bytes for ulm_pair_planes on an input list of `capacity` records. */
+int32_t ulm_pair_workspace_size(const ulm_ctx_t *ctx, int32_t capacity, size_t *bytes);
+
+/*
+ * Projection-based 3D localisation (Section II-A4): pair the localisations of
+ * the two orthogonal planes of each frame.  An XZ record i (orientation 0) and a
+ * YZ record j (orientation 1) of the same frame are candidates when
+ * |z_i - z_j| <= 1 (one voxel axially) and I_i / I_j lies in [0.9, 1.11]
+ * (intensities = the records' envelope values); with B slabs, j's y must lie in
+ * i's slab and i's x in j's slab.  A pair is kept when each is the other's
+ * candidate closest to a unit ratio, max(I_i/I_j, I_j/I_i) (ties to the smaller
+ * index); its 3D position is (x_i, y_j, (z_i + z_j) / 2).
+ *   locs   [capacity] ulm_loc_t, device, sorted by (plane, frame) as the
+ *          localisers write them; the first min(*count, capacity) are used.
+ *   out    [out_capacity] ulm_loc3d_t, device: pairs sorted by (frame, idx_xz);
+ *   out_count int32, device: total pairs (may exceed out_capacity; then
+ *          ulm_check_status(ctx, ws, out_count, out_capacity) returns OVERFLOW).
+ *   pws    workspace of at least ulm_pair_workspace_size(ctx, capacity) bytes.
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
+                        int32_t capacity, ulm_loc3d_t *out, int32_t out_capacity,
+                        int32_t *out_count, void *pws, size_t pws_bytes, void *stream);
 
 /*
  * Learned localiser: a CNN alternative to the NCC step (the paper's outlook,

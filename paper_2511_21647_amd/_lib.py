@@ -40,7 +40,8 @@ EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
            "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
            "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
            "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
-           "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize")
+           "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize",
+           "ulm_pair_workspace_size", "ulm_pair_planes")
 
 
 class ULMError(RuntimeError):
@@ -78,6 +79,10 @@ LOC_DTYPE = np.dtype([("plane", np.int32), ("frame", np.int32), ("iz", np.int32)
                       ("iu", np.int32), ("z", np.float32), ("u", np.float32),
                       ("ncc", np.float32), ("intensity", np.float32)])
 LOC_WORDS = 8
+# ulm_loc3d_t: int32 frame; float32 x, y, z, i_xz, i_yz; int32 idx_xz, idx_yz (32 bytes)
+LOC3D_DTYPE = np.dtype([("frame", np.int32), ("x", np.float32), ("y", np.float32),
+                        ("z", np.float32), ("i_xz", np.float32), ("i_yz", np.float32),
+                        ("idx_xz", np.int32), ("idx_yz", np.int32)])
 
 
 def _load():
@@ -113,6 +118,8 @@ def _load():
                                 i32, vp, vp, sz, vp], i32),
         "ulm_cnn_localize": ([vp, vp, vp, ctypes.c_float, i32, i32, vp, i32, vp, vp, sz, vp, sz,
                               vp], i32),
+        "ulm_pair_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
+        "ulm_pair_planes": ([vp, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -396,11 +403,23 @@ def ulm_cnn_localize_workspace_size(ctx: Context, batch: int, precision: int = U
     return n.value
 
 
+def _require_rows(t, rows, name):
+    """t: contiguous int32 CUDA tensor [>= rows][8] of 32-byte records."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ULMError(ULM_ERR_INVALID_ARG, f"{name} must be a CUDA tensor")
+    if (t.dtype != torch.int32 or t.dim() != 2 or t.shape[1] != 8 or t.shape[0] < rows
+            or not t.is_contiguous()):
+        raise ULMError(ULM_ERR_INVALID_ARG,
+                       f"{name}: expected contiguous int32 [>= {rows}][8], got {t.dtype} "
+                       f"{tuple(t.shape)}")
+
+
 def _ws(ws, nbytes, device):
     if ws is None:
         return Workspace(nbytes, device)
     if ws.nbytes < nbytes:
-        raise ULMError(ULM_ERR_INVALID_ARG, f"CNN workspace holds {ws.nbytes} bytes, needs {nbytes}")
+        raise ULMError(ULM_ERR_INVALID_ARG, f"workspace holds {ws.nbytes} bytes, needs {nbytes}")
     return ws
 
 
@@ -506,3 +525,39 @@ def ulm_cnn_localize(ctx: Context, params, filtered, capacity: int, threshold: f
                                  _ptr(count), ctx.ws_ptr, ctx.ws_bytes, ws.ptr, ws.nbytes,
                                  _stream(stream)))
     return locs, count
+
+
+# ---------------------------------------------------------------- plane pairing
+
+def ulm_pair_workspace_size(ctx: Context, capacity: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.ulm_pair_workspace_size(ctx.handle, int(capacity), ctypes.byref(n)))
+    return n.value
+
+
+def ulm_pair_planes(ctx: Context, locs, count, capacity: int, out_capacity: int, out=None,
+                    out_count=None, ws=None, stream=None):
+    """Pairs XZ and YZ localisations (records sorted by plane and frame) into 3D
+    localisations; returns (out int32 [out_capacity][8] of ulm_loc3d_t, out_count)."""
+    torch = _torch()
+    _require_rows(locs, capacity, "locs")
+    _require(count, torch.int32, (1,), "count")
+    dev = locs.device
+    if out is None:
+        out = torch.empty((max(out_capacity, 1), 8), dtype=torch.int32, device=dev)
+    if out_count is None:
+        out_count = torch.zeros(1, dtype=torch.int32, device=dev)
+    _require_rows(out, out_capacity, "out")
+    _require(out_count, torch.int32, (1,), "out_count")
+    ws = _ws(ws, ulm_pair_workspace_size(ctx, capacity), dev)
+    _check(_lib.ulm_pair_planes(ctx.handle, _ptr(locs), _ptr(count), int(capacity), _ptr(out),
+                                int(out_capacity), _ptr(out_count), ws.ptr, ws.nbytes,
+                                _stream(stream)))
+    return out, out_count
+
+
+def loc3d_to_numpy(out, count) -> np.ndarray:
+    """Copy the first min(count, capacity) 3D records to a structured numpy array."""
+    n = int(count.item()) if hasattr(count, "item") else int(count)
+    n = min(n, out.shape[0])
+    return out[:n].contiguous().cpu().numpy().view(LOC3D_DTYPE).reshape(-1)

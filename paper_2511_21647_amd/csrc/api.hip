@@ -28,6 +28,10 @@ hipError_t launch_sim(const ulm_ctx *ctx, const double *pos, const double *amp, 
 size_t ncc_lds_bytes(int nu, int half);
 hipError_t launch_frame_max(const float2 *P, float *fmax, int n_img, int npix, hipStream_t st);
 size_t cnn_workspace_bytes(int B, int H, int W, bool fp32, bool train);
+size_t pair_workspace_bytes(int planes, int F, int capacity);
+hipError_t launch_pairing(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
+                          int capacity, ulm_loc3d_t *out, int out_capacity, int *out_count,
+                          char *pws, hipStream_t st);
 size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
 hipError_t cnn_images(const float2 *P, const float *fmax, float *x0, int npix, int n0, int nb,
                       hipStream_t st);
@@ -126,8 +130,6 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.hvec = take(sizeof(double2) * planes * F * F);
     w.vbuf = take(sizeof(double2) * planes * 2 * F);
     w.pbuf = take(sizeof(double2) * planes * 2 * F);
-    w.dots = take(sizeof(double) * planes * 2 * 64);
-    w.scal = take(sizeof(double) * planes * 4);
     w.bar = take(sizeof(int) * planes);
     w.eflag = take(sizeof(int) * planes);
     w.fmax = take(sizeof(float) * planes * F);
@@ -599,5 +601,28 @@ extern "C" int32_t ulm_cnn_localize(ulm_ctx_t *ctx, const float *params, const f
     HIP_TRY(cnn_localize(params, (const float2 *)filtered, fmax, threshold, n_img, g.n_frames, g.nz,
                          g.nu, batch, fp32, locs, capacity, count, status, (char *)cnn_ws, st),
             "ulm_cnn_localize");
+    return ULM_OK;
+}
+
+// ---------------------------------------------------------------- plane pairing
+
+extern "C" int32_t ulm_pair_workspace_size(const ulm_ctx_t *ctx, int32_t capacity, size_t *bytes) {
+    if (!ctx || !bytes || capacity < 0) return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    *bytes = pair_workspace_bytes(ctx->geo.n_planes, ctx->geo.n_frames, std::max(capacity, 1));
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
+                                   int32_t capacity, ulm_loc3d_t *out, int32_t out_capacity,
+                                   int32_t *out_count, void *pws, size_t pws_bytes, void *stream) {
+    if (!ctx || !count || !out_count || capacity < 0 || out_capacity < 0 ||
+        (capacity > 0 && !locs) || (out_capacity > 0 && !out))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    if (!pws || pws_bytes < pair_workspace_bytes(ctx->geo.n_planes, ctx->geo.n_frames, std::max(capacity, 1)))
+        return fail(ULM_ERR_INVALID_ARG, "pairing workspace missing or too small");
+    if (((uintptr_t)pws & 255) != 0) return fail(ULM_ERR_INVALID_ARG, "pairing workspace not 256-byte aligned");
+    HIP_TRY(launch_pairing(ctx, locs, count, capacity, out, out_capacity, out_count, (char *)pws,
+                           (hipStream_t)stream),
+            "ulm_pair_planes");
     return ULM_OK;
 }

@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void cnn_head_decode_kernel(
     constexpr int HC = kTileCols + 2;
     __shared__ __attribute__((aligned(16))) T whs[kR2 * Lds<T>::wh];
     __shared__ float bhs[kR2];
-    __shared__ float hs[3][HC][kR2];
+    __shared__ float hs[3][HC][kR2 + 1];       // +1: the decode's 64 lanes (8 columns x 8 fine rows) hit 64 banks
     __shared__ int wave_tot[4];
     __shared__ int base_s;
     stage_head<T>(p, whs, bhs);

@@ -66,8 +66,6 @@ struct Workspace {
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
     size_t vbuf, pbuf;  // [planes][2][F] c128      column / p exchange (by step parity)
-    size_t dots;        // [planes][2][64] f64      partial p^H v per work-group (by parity)
-    size_t scal;        // [planes][4] f64
     size_t bar;         // [planes] i32             grid-barrier counters
     size_t eflag;       // [planes] i32
     size_t fmax;        // [planes][F] f32
@@ -83,6 +81,15 @@ template <typename T> __host__ __device__ inline T cdiv(T a, T b) { return (a + 
 
 // Columns of the padded clutter subspace the removal kernel is compiled for.
 inline int removal_cols(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 24 ? 24 : 32; }
+
+// Work-group remap so that consecutive logical work-groups land on the same
+// XCD (the dispatcher deals work-groups round-robin over the 8 XCDs), so
+// work-groups that read the same data share one L2.
+__device__ inline int xcd_remap(int lin, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = lin & 7, s = lin >> 3;
+    return x * q + min(x, r) + s;
+}
 
 }  // namespace ulm
 

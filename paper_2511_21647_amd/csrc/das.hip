@@ -1,0 +1,181 @@
+// Stage 1 of the two-stage row-column beamforming (paper Section II-A1): per
+// transmit, delay-and-sum of all receive elements into the reference slice
+// S_k(u, z).  One work-group owns an 8 x 32 pixel tile, one transmit and 16
+// frames: the delay, interpolation weight and phasor of each (pixel, element)
+// pair are read once and applied to all 16 frames.  For each element the
+// samples that the tile can reach (at most 64 or 128, exact window from the
+// host) are staged in LDS, double-buffered: the next element's global loads are
+// in flight during the current element's arithmetic, so the gathers hit LDS,
+// not the cache.
+#include "common.h"
+
+namespace ulm {
+
+// Stage-1 DAS.  The receive part of each (pixel, element) delay and phasor
+// comes from host-computed FP64 tables (rounded to FP32):
+//   rxd[e][pixel] = (r - z) fs / c,   rxp[e][pixel] = exp(i 2 pi f0 (r - z) / c),
+// r = sqrt((u - u_e)^2 + z^2); the per-(depth, transmit) part is
+//   (tau_tx + z / c - t_start) fs = sti[k][z] + stz[k][z] (integer + fraction),
+//   phz[k][z] = exp(i 2 pi f0 (tau_tx - z / c)).
+// The sample index is sti + (rxd + stz): the FP32 sum stays below a few hundred
+// samples, and the host forms the same sum to find each (transmit, tile,
+// element) window start win[...] exactly.
+// LDS holds, per staged sample, (IQ[s], IQ[s+1] - IQ[s]) so the interpolation
+// is two FMAs per frame.
+template <int FB, int LEN>
+__global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
+    const float2 *__restrict__ iq, float2 *__restrict__ S, const float *__restrict__ stz,
+    const int *__restrict__ sti, const float2 *__restrict__ phz, const float *__restrict__ rxd,
+    const float2 *__restrict__ rxp, const int *__restrict__ win, Geometry g, int n_tu, int n_tz,
+    int n_fb)
+{
+    const int n_tiles = n_tu * n_tz;
+    const int n_wg = n_tiles * n_fb * 2 * g.n_angles;
+    const int w = xcd_remap(blockIdx.x, n_wg);
+    const int tile = w % n_tiles;
+    const int fb = (w / n_tiles) % n_fb;
+    const int ok = w / (n_tiles * n_fb);
+    const int o = ok / g.n_angles, k = ok % g.n_angles;
+    const int tz = tile / n_tu, tu = tile % n_tu;
+
+    const int t = threadIdx.x;
+    const int iz = tz * kDasTileZ + t / kDasTileU;
+    const int iu = tu * kDasTileU + t % kDasTileU;
+    const bool valid = iz < g.nz && iu < g.nu;
+    const int izc = min(iz, g.nz - 1), iuc = min(iu, g.nu - 1);
+    const int npix = g.nz * g.nu;
+    const int pix = izc * g.nu + iuc;
+    const float stz_p = stz[k * g.nz + izc];
+    const int sti_p = sti[k * g.nz + izc];
+    const int *wj = win + (size_t)(k * n_tiles + tile) * g.n_elem;
+
+    __shared__ float4 buf[2][FB][LEN];
+
+    const size_t frame_stride = (size_t)2 * g.n_angles * g.n_elem * g.n_samp;
+    const int f0 = fb * FB;
+    const float2 *blk = iq + ((size_t)o * g.n_angles + k) * g.n_elem * g.n_samp;
+
+    // staging map: each thread stages runs of 4 consecutive samples of one frame
+    // (5 loads give the 4 samples and their 4 forward differences)
+    constexpr int RUNS = LEN / 4;
+    constexpr int NQ = FB * RUNS / kDasThreads;
+    static_assert(NQ >= 1 && FB * RUNS % kDasThreads == 0, "staging map");
+    float4 st[NQ][4];
+    float prx;
+    float2 pph;
+    auto load = [&](int j) {
+        const int s_lo = wj[j];
+        const float2 *ch = blk + (size_t)j * g.n_samp;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * kDasThreads;
+            const int fl = e / RUNS, run = e % RUNS;
+            const int f = f0 + fl;
+            const float2 *row = ch + (size_t)min(f, g.n_frames - 1) * frame_stride;
+            const int gs = s_lo + 4 * run;
+            float2 x[5];
+            if (gs >= 0 && gs + 4 < g.n_samp) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) x[i] = row[gs + i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const int gi = gs + i;
+                    x[i] = (gi >= 0 && gi < g.n_samp) ? row[min(max(gi, 0), g.n_samp - 1)]
+                                                      : make_float2(0.f, 0.f);
+                }
+            }
+            // frames past the end read the last frame; their sums are never written
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                st[q][i] = make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
+        }
+        prx = rxd[(size_t)j * npix + pix];
+        pph = rxp[(size_t)j * npix + pix];
+    };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * kDasThreads;
+            const int fl = e / RUNS, run = e % RUNS;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) buf[b][fl][4 * run + i] = st[q][i];
+        }
+    };
+
+    float2 acc[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) acc[f] = make_float2(0.f, 0.f);
+
+    load(0);
+    store(0);
+    float crx = prx;
+    float2 cph = pph;
+    int s_lo = wj[0];
+    __syncthreads();
+
+    for (int j = 0; j < g.n_elem; ++j) {
+        const int cur = j & 1;
+        // the last iteration re-stages the last element into the idle buffer, so
+        // the loop body has no branch around the stores
+        const int jn = min(j + 1, g.n_elem - 1);
+        load(jn);
+        const float s = crx + stz_p;
+        const float fl = floorf(s);
+        const float fr = s - fl;
+        const int idx = min(max((int)fl + sti_p - s_lo, 0), LEN - 1);
+        // four LDS reads in flight: frame f + 4 is requested while frame f is applied
+        float4 vq[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) vq[f] = buf[cur][f][idx];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            const float4 v = vq[f & 3];
+            if (f + 4 < FB) vq[f & 3] = buf[cur][f + 4][idx];
+            const float xr = fmaf(fr, v.z, v.x);
+            const float xi = fmaf(fr, v.w, v.y);
+            acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));
+            acc[f].y = fmaf(cph.x, xi, fmaf(cph.y, xr, acc[f].y));
+        }
+
+        store(cur ^ 1);
+        crx = prx;
+        cph = pph;
+        s_lo = wj[jn];
+        __syncthreads();
+    }
+
+    if (!valid) return;
+    const float2 ph = phz[k * g.nz + izc];
+    float2 *dst = S + ((size_t)(o * g.n_angles + k) * g.n_frames) * npix + (size_t)iz * g.nu + iu;
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        if (f0 + f < g.n_frames) {
+            float2 v;
+            v.x = acc[f].x * ph.x - acc[f].y * ph.y;
+            v.y = acc[f].x * ph.y + acc[f].y * ph.x;
+            dst[(size_t)(f0 + f) * npix] = v;
+        }
+    }
+}
+
+template <int FB, int LEN>
+static void das_launch(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st)
+{
+    const Geometry &g = ctx->geo;
+    const Tables &tb = ctx->tab;
+    const int n_tu = cdiv(g.nu, kDasTileU), n_tz = cdiv(g.nz, kDasTileZ);
+    const int n_fb = cdiv(g.n_frames, FB);
+    const int n_wg = n_tu * n_tz * n_fb * 2 * g.n_angles;
+    hipLaunchKernelGGL((das_stage1_kernel<FB, LEN>), dim3(n_wg), dim3(kDasThreads), 0, st, iq,
+                       slices, tb.stx, tb.sti, tb.phz, tb.rxd, tb.rxp, tb.win, g, n_tu, n_tz, n_fb);
+}
+
+hipError_t launch_stage1(const ulm_ctx *ctx, const float2 *iq, float2 *slices, hipStream_t st)
+{
+    if (ctx->tab.das_len == 64) das_launch<kDasFrames, 64>(ctx, iq, slices, st);
+    else das_launch<kDasFrames, 128>(ctx, iq, slices, st);
+    return hipGetLastError();
+}
+
+}  // namespace ulm

@@ -23,7 +23,7 @@
 // Grid barriers spin on an agent-scope counter with a bounded wait: a work-
 // group that waits too long flags the status word and exits, so every wave
 // always finishes.
-#include "common.h"
+#include "eigen.h"
 
 #include <float.h>
 
@@ -33,25 +33,6 @@ constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
 constexpr int kCoopRows = 8;     // back-transformation rows per lane: F <= 512
 
-struct EigArgs {
-    const double2 *C;   // [planes][F][F] covariance (full Hermitian)
-    double2 *H;         // [planes][F][F] row k: Householder vector v_k (entries k+1..F-1)
-    double2 *tau;       // [planes][F]
-    double *d, *e;      // [planes][F]
-    double *lam;        // [planes][F] eigenvalues, descending
-    double *lam_out;    // optional copy of lam
-    double2 *V;         // [planes][F][c] clutter eigenvectors
-    double *tscr;       // [planes][c][6][F]
-    double2 *xscr;      // [planes][c][F]
-    double2 *vbuf;      // [planes][F] reflector of the current step
-    double2 *pbuf;      // [planes][F]
-    double *dots;       // unused
-    double *scal;       // unused
-    int *bar;           // [planes] barrier counters, zero at launch
-    int *flag;          // [planes] non-finite input
-    int *status;
-    int F, c, W, planes;
-};
 
 __device__ inline double2 cmul2(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -180,7 +161,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
 {
     const int g = blockIdx.x, xcd = g & 7, slot = g >> 3;
     const int W = a.W, F = a.F, c = a.c;
-    const int plane = xcd + 8 * (slot / W), w = slot % W;
+    const int plane = a.plane0 + xcd + 8 * (slot / W), w = slot % W;
     if (plane >= a.planes) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int ncol = cdiv(F, W);
@@ -566,13 +547,31 @@ size_t eigen_coop_lds(int F, int c) {
     return std::max(red_b, tail_b) + 64 * sizeof(double);
 }
 
+// A cooperative launch needs every work-group resident at once, so the planes
+// are solved in groups: as many whole rounds of 8 planes (one per XCD) as fit.
 hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st) {
-    const int slots = cdiv(args.planes, 8) * args.W;
-    dim3 grid(8 * slots), block(kCoopThreads);
-    EigArgs a = args;
-    void *params[] = {&a};
-    return hipLaunchCooperativeKernel((const void *)eigen_coop_kernel, grid, block, params,
-                                      (unsigned)eigen_coop_lds(args.F, args.c), st);
+    const unsigned lds = (unsigned)eigen_coop_lds(args.F, args.c);
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)eigen_coop_kernel,
+                                                         kCoopThreads, lds);
+    if (e != hipSuccess) return e;
+    const int resident = per_cu * ncu;
+    const int group = resident / (8 * args.W) * 8;           // whole rounds of 8 planes
+    if (group == 0) return hipErrorCooperativeLaunchTooLarge;
+    for (int p0 = 0; p0 < args.planes; p0 += group) {
+        EigArgs a = args;
+        a.plane0 = p0;
+        a.planes = std::min(args.planes, p0 + group);        // planes [p0, a.planes)
+        const int n = a.planes - p0;
+        dim3 grid(8 * cdiv(n, 8) * args.W), block(kCoopThreads);
+        void *params[] = {&a};
+        e = hipLaunchCooperativeKernel((const void *)eigen_coop_kernel, grid, block, params, lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace ulm

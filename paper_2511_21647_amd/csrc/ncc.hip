@@ -421,6 +421,13 @@ hipError_t launch_frame_max(const float2 *P, float *fmax, int n_img, int npix, h
     return hipGetLastError();
 }
 
+// Exclusive scan of n counts into off, the total into *count.
+hipError_t launch_scan(const int *cnt, int *off, int n, int *count, hipStream_t st)
+{
+    hipLaunchKernelGGL(loc_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, off, n, count);
+    return hipGetLastError();
+}
+
 // Exclusive scan of per-slot counts, then each slot's records to its offset.
 hipError_t launch_compact(const int *cnt, int *off, int nslots, int *count, const ulm_loc_t *staged,
                           int cap, ulm_loc_t *locs, int capacity, hipStream_t st)

@@ -9,34 +9,12 @@
 // Layout: a plane is stored frame-major, [F][n_pix] complex64, i.e. the
 // transpose of the Casorati matrix; the frame axis is the Gram's output axis
 // and the pixel axis its reduction axis.
-#include "common.h"
+#include "eigen.h"
 
 #include <float.h>
 
 namespace ulm {
 
-struct EigArgs {
-    const double2 *C;
-    double2 *H;
-    double2 *tau;
-    double *d, *e;
-    double *lam;
-    double *lam_out;
-    double2 *V;
-    double *tscr;
-    double2 *xscr;
-    double2 *vbuf;
-    double2 *pbuf;
-    double *dots;
-    double *scal;
-    int *bar;
-    int *flag;
-    int *status;
-    int F, c, W, planes;
-};
-int eigen_coop_width(int F);
-size_t eigen_coop_lds(int F, int c);
-hipError_t launch_eigen_coop(const EigArgs &args, hipStream_t st);
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -713,8 +691,6 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         a.xscr = (double2 *)(ws + w.xscratch);
         a.vbuf = (double2 *)(ws + w.vbuf);
         a.pbuf = (double2 *)(ws + w.pbuf);
-        a.dots = (double *)(ws + w.dots);
-        a.scal = (double *)(ws + w.scal);
         a.bar = (int *)(ws + w.bar);
         a.flag = (int *)(ws + w.eflag);
         a.status = status;
@@ -722,6 +698,7 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         a.c = c;
         a.W = eigen_coop_width(F);
         a.planes = planes;
+        a.plane0 = 0;
         if ((e = launch_eigen_coop(a, st)) != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(eigen_kernel, dim3(planes), dim3(kEigThreads), 0, st, C,

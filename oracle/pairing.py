@@ -38,15 +38,12 @@ def _slab(pix, per):
     return s.astype(np.int64)
 
 
-def pair_frame(xz, yz, per=None):
-    """xz, yz: arrays with fields z, u, intensity (float32) and block.  Returns
-    a list of (i, j) index pairs in increasing i."""
-    n, m = len(xz), len(yz)
-    if n == 0 or m == 0:
-        return []
-    zi = xz["z"].astype(np.float32)[:, None]
+def _cost_rows(xz, yz, rows, per):
+    """Cost of pairing XZ records `rows` with every YZ record: max(rho, 1/rho)
+    for candidates, +inf otherwise (FP32)."""
+    zi = xz["z"][rows].astype(np.float32)[:, None]
     zj = yz["z"].astype(np.float32)[None, :]
-    Ii = xz["intensity"].astype(np.float32)[:, None]
+    Ii = xz["intensity"][rows].astype(np.float32)[:, None]
     Ij = yz["intensity"].astype(np.float32)[None, :]
     with np.errstate(divide="ignore", invalid="ignore"):
         rho = (Ii / Ij).astype(np.float32)
@@ -55,31 +52,50 @@ def pair_frame(xz, yz, per=None):
     ok &= (Ii > 0) & (Ij > 0)
     if per is not None:
         # slab consistency: y of the YZ record in the XZ record's slab, and vice versa
-        ok &= _slab(yz["u"], per)[None, :] == xz["block"][:, None]
-        ok &= _slab(xz["u"], per)[:, None] == yz["block"][None, :]
-    cost = np.where(ok, np.maximum(rho, inv), np.float32(np.inf)).astype(np.float32)
+        ok &= _slab(yz["u"], per)[None, :] == xz["block"][rows][:, None]
+        ok &= _slab(xz["u"][rows], per)[:, None] == yz["block"][None, :]
+    return np.where(ok, np.maximum(rho, inv), np.float32(np.inf)).astype(np.float32)
+
+
+def pair_frame(xz, yz, per=None, chunk=1024):
+    """xz, yz: arrays with fields z, u, intensity (float32) and block.  Returns
+    a list of (i, j) index pairs in increasing i.  The cost matrix is formed
+    `chunk` XZ rows at a time; every record's best candidate is the first
+    minimum in index order."""
+    n, m = len(xz), len(yz)
+    if n == 0 or m == 0:
+        return []
     best_j = np.full(n, -1)
-    for i in range(n):
-        if np.isfinite(cost[i]).any():
-            best_j[i] = int(np.argmin(cost[i]))          # first minimum = smaller index
+    col_min = np.full(m, np.float32(np.inf), dtype=np.float32)
     best_i = np.full(m, -1)
-    for j in range(m):
-        if np.isfinite(cost[:, j]).any():
-            best_i[j] = int(np.argmin(cost[:, j]))
+    for r0 in range(0, n, chunk):
+        rows = np.arange(r0, min(n, r0 + chunk))
+        cost = _cost_rows(xz, yz, rows, per)
+        for a, i in enumerate(rows):
+            if np.isfinite(cost[a]).any():
+                best_j[i] = int(np.argmin(cost[a]))          # first minimum = smaller index
+        cm = cost.min(axis=0)
+        ca = rows[0] + np.argmin(cost, axis=0)               # first row reaching the chunk's minimum
+        upd = cm < col_min                                   # strict: earlier chunks keep ties
+        col_min = np.where(upd, cm, col_min)
+        best_i = np.where(upd & np.isfinite(cm), ca, best_i)
     return [(i, int(best_j[i])) for i in range(n) if best_j[i] >= 0 and best_i[best_j[i]] == i]
 
 
-def pair_localisations(locs, n_blocks: int, nv: int):
+def pair_localisations(locs, n_blocks: int, nv: int, frames=None):
     """locs: records (plane, frame, z, u, intensity) of both orientations, plane =
     o * n_blocks + b.  Returns a structured array of 3D localisations sorted by
     (frame, XZ record index): frame, x, y, z (plane pixels), the two
-    intensities and the indices of the paired records in `locs`."""
+    intensities and the indices of the paired records in `locs`.  `frames`
+    limits the pairing to those frames (frames are paired independently)."""
     out = []
     per = -(-nv // n_blocks)
     locs = np.asarray(locs)
     idx = np.arange(len(locs))
-    frames = np.unique(locs["frame"]) if len(locs) else []
-    for f in frames:
+    todo = np.unique(locs["frame"]) if len(locs) else []
+    if frames is not None:
+        todo = [f for f in todo if f in set(int(x) for x in frames)]
+    for f in todo:
         sel = locs["frame"] == f
         a_mask = sel & (locs["plane"] < n_blocks)
         b_mask = sel & (locs["plane"] >= n_blocks)

@@ -147,3 +147,20 @@ def test_synthetic_lists_recover_most_points():
         found += len(got)
     n = sum(len(t) for t in truth)
     assert found >= 0.7 * n, (found, n)
+
+
+def test_chunked_cost_matrix_gives_the_same_pairs():
+    """Forming the cost matrix a few rows at a time changes nothing, ties
+    included (equal intensities everywhere make every candidate cost 1)."""
+    rng = np.random.default_rng(0)
+    dt = [("z", "f4"), ("u", "f4"), ("intensity", "f4"), ("block", "i8")]
+    for equal in (False, True):
+        xz, yz = np.zeros(300, dt), np.zeros(280, dt)
+        for a in (xz, yz):
+            a["z"] = rng.uniform(0, 5, len(a))
+            a["u"] = rng.uniform(0, 64, len(a))
+            a["intensity"] = 1.0 if equal else rng.uniform(0.9, 1.1, len(a))
+            a["block"] = rng.integers(0, 4, len(a))
+        for per in (None, 16):
+            whole = pairing.pair_frame(xz, yz, per, chunk=100000)
+            assert pairing.pair_frame(xz, yz, per, chunk=7) == whole and len(whole) >= 3

@@ -9,7 +9,11 @@ is already resident in HBM: stage-1 DAS -> stage-2 projection -> clutter filter
             (`value` is this form's ms/ensemble)
   bf16_cnn  BF16 hi/lo split Gram and removal with FP32 accumulation, FP64
             eigen; the learned CNN localiser (BF16 activations) with the
-            trained weights in paper_2511_21647_amd/weights/  The IQ comes from the library's forward simulator of a
+            trained weights in paper_2511_21647_amd/weights/
+  slab_p8   the paper's sub-block projection: slabs of 8 slices (2 x 35
+            planes), plain filter and NCC on every slab plane, then the
+            XZ/YZ pairing into 3D localisations
+The IQ comes from the library's forward simulator of a
 synthetic medium shaped like the paper's pig-kidney acquisition (2000 MBs on
 vessel splines, 20000 tissue scatterers 40 dB above the MBs, rigid 0.2 mm
 1 Hz motion), generated on the GPU before timing.
@@ -89,7 +93,7 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     import torch
     import paper_2511_21647_amd as ulm
 
-    cap = 4_000_000
+    cap = 4_000_000 if form != "slab_p8" else 1 << 25
     proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device="cuda")
     eig = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device="cuda")
     locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
@@ -97,6 +101,12 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     cws = None
     if form == "bf16_cnn":
         cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(ctx, 64), "cuda")
+    pair = form == "slab_p8"
+    if pair:
+        pair_cap = 1 << 24
+        pairs = torch.empty((pair_cap, 8), dtype=torch.int32, device="cuda")
+        pair_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        pws = ulm.Workspace(ulm.ulm_pair_workspace_size(ctx, cap), "cuda")
 
     def step(ev=None):
         if ev: ev[0].record()
@@ -106,18 +116,21 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
         if ev: ev[2].record()
         ulm.svd_clutter_filter(ctx, proj, eig)
         if ev: ev[3].record()
-        if form == "plain":
-            ulm.ncc_localize(ctx, proj, cap, locs, count)
-        else:
+        if form == "bf16_cnn":
             ulm.ulm_cnn_localize(ctx, cnn_params, proj, cap, ulm.CNN_THRESHOLD, 64, ulm.ULM_CNN_BF16, locs,
                                  count, ws=cws)
+        else:
+            ulm.ncc_localize(ctx, proj, cap, locs, count)
         if ev: ev[4].record()
+        if pair:
+            ulm.ulm_pair_planes(ctx, locs, count, cap, pair_cap, pairs, pair_count, ws=pws)
+            if ev: ev[5].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     ulm.ulm_check_status(ctx, count, cap)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -127,13 +140,55 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     ulm.ulm_check_status(ctx, count, cap)
     ms_step = (t1 - t0) * 1e3 / args.steps
     names = ["das_stage1", "stage2_projection", "clutter_filter",
-             "ncc_localize" if form == "plain" else "cnn_localize"]
+             "cnn_localize" if form == "bf16_cnn" else "ncc_localize"] + (["pairing_3d"] if pair else [])
     stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps
              for i, n in enumerate(names)}
     n_det = int(count.item())
+    if pair:
+        ulm.ulm_check_status(ctx, pair_count, pair_cap)
+        n_det = (n_det, int(pair_count.item()))
+        del pairs, pws
     del proj, eig, locs, cws
     torch.cuda.empty_cache()
     return ms_step, stage, n_det
+
+
+MOTION_MAX_LAG = 8
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def time_motion(cfg, ctx, args):
+    """Rigid motion estimation on the stage-1 slices left in the workspace by
+    the last timed step (lag window +-8 px, reference frame 0): ms per
+    ensemble and the correlation contraction's rate against the FP32 MFMA
+    peak (2 flop per pixel, lag, frame and slice)."""
+    import torch
+    import paper_2511_21647_amd as ulm
+
+    S = ulm.ulm_stage1_slices(ctx)
+    ws = ulm.Workspace(ulm.ulm_motion_workspace_size(ctx, MOTION_MAX_LAG), "cuda")
+    F, K = cfg.seq.n_frames, cfg.n_angles
+    disp = torch.empty((2, K, F, 2), dtype=torch.float32, device="cuda")
+    mot = torch.empty((F, 3), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        ulm.ulm_motion_estimate(ctx, S, 0, MOTION_MAX_LAG, disp, mot, ws=ws)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        ulm.ulm_motion_estimate(ctx, S, 0, MOTION_MAX_LAG, disp, mot, ws=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    nl = (2 * MOTION_MAX_LAG + 1) ** 2
+    flops = 2.0 * 2 * K * F * nl * cfg.grid.nz * cfg.grid.nu
+    tf = flops / (ms * 1e-3) / 1e12
+    del ws
+    return {"ms_per_ensemble": round(ms, 3), "max_lag": MOTION_MAX_LAG, "ref_frame": 0,
+            "roofline": {"bound": "mfma", "kernel": "ulm_motion_estimate (its four kernels)",
+                         "achieved": round(tf, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / FP32_MFMA_PEAK_TFLOPS, 4),
+                         "algorithmic_flops": flops}}
 
 
 def run_gpu(args):
@@ -148,6 +203,8 @@ def run_gpu(args):
                                                                        stage.items()},
                       "detections": n}
     log(f"plain: {ms:.2f} ms/ensemble {stage}")
+    forms["plain"]["motion_estimation"] = time_motion(cfg, ctx, args)
+    log(f"motion estimation: {forms['plain']['motion_estimation']}")
     if args.form == "both" and os.path.exists(WEIGHTS):
         ctx_b = ulm.Context(cfg, precision=ulm.ULM_PREC_BF16X3)
         params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()
@@ -159,6 +216,18 @@ def run_gpu(args):
         ctx_b.close()
     elif args.form == "both":
         forms["bf16_cnn"] = {"skipped": f"no trained weights at {WEIGHTS}"}
+    if args.form == "both":
+        # the paper's sub-block form: slabs of 8 slices, 2 x 35 planes, 3D pairing
+        from synth import with_blocks
+        cfg_s = with_blocks(cfg, -(-cfg.grid.nv // 8))
+        ctx_s = ulm.Context(cfg_s)
+        ms_s, stage_s, (n_s, n_pairs) = run_form("slab_p8", cfg_s, ctx_s, iq, args)
+        forms["slab_p8"] = {"ms_per_ensemble": round(ms_s, 3),
+                            "planes": [2 * cfg_s.grid.n_blocks, cfg_s.grid.nz, cfg_s.grid.nu],
+                            "stages_ms": {k: round(v, 3) for k, v in stage_s.items()},
+                            "detections": n_s, "pairs_3d": n_pairs}
+        log(f"slab_p8: {ms_s:.2f} ms/ensemble {stage_s}")
+        ctx_s.close()
     return cfg, ms, stage, n, forms
 
 
@@ -340,7 +409,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", choices=["plain", "both"], default="both",
-                    help="time the plain path only, or also the BF16 + CNN form")
+                    help="time the plain path only, or also the BF16 + CNN and slab forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-das", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))

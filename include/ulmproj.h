@@ -250,6 +250,56 @@ int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *co
                         int32_t capacity, ulm_loc3d_t *out, int32_t out_capacity,
                         int32_t *out_count, void *pws, size_t pws_bytes, void *stream);
 
+/* Byte offset of the stage-1 reference slices S[2][K][F][Nz][Nu] (c64) inside
+ * the workspace, where rca_beamform_stage1 leaves them. */
+int32_t ulm_slices_offset(const ulm_ctx_t *ctx, size_t *offset);
+
+/* Workspace bytes for ulm_motion_estimate with lag window `max_lag`. */
+int32_t ulm_motion_workspace_size(const ulm_ctx_t *ctx, int32_t max_lag, size_t *bytes);
+
+/*
+ * Rigid motion estimation on the stage-1 reference slices (Section II-A3): each
+ * frame of each of the 2K slices is compared with frame `ref_frame` of the same
+ * slice by the normalised cross-correlation of the two envelopes (|S|, each made
+ * zero-mean; circular in the Nz x Nu grid, as an unpadded FFT correlation is);
+ * the displacement is the correlation's peak within |dz|, |du| <= max_lag
+ * (first maximum in raster order of (dz, du)), refined per axis by the 3-point
+ * Gaussian fit of the localiser (parabolic where a value is <= 0, clamped to
+ * +-0.5, none on the window edge).  The K displacements of each orientation are
+ * averaged; the 3D motion takes x from the RC (x-z) slices, y from the CR (y-z)
+ * slices and the mean of their axial parts.  A frame whose content moved by +d
+ * pixels (frame(p) = reference(p - d)) gives +d.
+ *   slices  [2][K][F][Nz][Nu] c64, device (e.g. the workspace at
+ *           ulm_slices_offset after rca_beamform_stage1).
+ *   disp    [2][K][F][2] f32, device: (dz, du) per slice and frame, pixels.
+ *   motion  [F][3] f32, device: (dx, dy, dz) per frame, pixels.
+ *   mws     workspace of at least ulm_motion_workspace_size(ctx, max_lag) bytes,
+ *           256-byte aligned.
+ *   max_lag 1..10, with 2 max_lag + 1 <= min(Nz, Nu).
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t ulm_motion_estimate(ulm_ctx_t *ctx, const float *slices, int32_t ref_frame,
+                            int32_t max_lag, float *disp, float *motion, void *mws,
+                            size_t mws_bytes, void *stream);
+
+/*
+ * MB separation (Section II-A5): at every pixel of every filtered plane, the
+ * F-point DFT over the frames, X[k] = sum_n x[n] exp(-2 pi i k n / F), an ideal
+ * band-pass mask per subset and the inverse DFT.  With H = (F - 1) / 2, "up"
+ * (MBs moving towards the probe, whose phase advances with this library's
+ * baseband convention) keeps bins k = 1..H and "down" bins F - H..F - 1; each
+ * direction is split by |k| into n_speed contiguous speed ranges, range s
+ * holding |k| in [1 + floor(s H / n_speed), 1 + floor((s + 1) H / n_speed)).
+ * The DC bin and, for even F, the Nyquist bin belong to no subset.
+ *   filtered [2][B][F][Nz][Nu] c64, device.
+ *   subsets  [2 n_speed][2][B][F][Nz][Nu] c64, device: up ranges 0..S-1 (slowest
+ *            first), then down ranges 0..S-1.
+ *   n_speed  1..8; F must be 2..512 with no prime factor above 7.
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t ulm_separate(ulm_ctx_t *ctx, const float *filtered, int32_t n_speed, float *subsets,
+                     void *stream);
+
 /*
  * Learned localiser: a CNN alternative to the NCC step (the paper's outlook,
  * Section IV, names deep-learning localisation as the way past NCC on dense MB

@@ -41,7 +41,8 @@ EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
            "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
            "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
            "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize",
-           "ulm_pair_workspace_size", "ulm_pair_planes")
+           "ulm_pair_workspace_size", "ulm_pair_planes", "ulm_slices_offset",
+           "ulm_motion_workspace_size", "ulm_motion_estimate", "ulm_separate")
 
 
 class ULMError(RuntimeError):
@@ -120,6 +121,10 @@ def _load():
                               vp], i32),
         "ulm_pair_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
         "ulm_pair_planes": ([vp, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "ulm_slices_offset": ([vp, ctypes.POINTER(sz)], i32),
+        "ulm_motion_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
+        "ulm_motion_estimate": ([vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
+        "ulm_separate": ([vp, vp, i32, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -561,3 +566,60 @@ def loc3d_to_numpy(out, count) -> np.ndarray:
     n = int(count.item()) if hasattr(count, "item") else int(count)
     n = min(n, out.shape[0])
     return out[:n].contiguous().cpu().numpy().view(LOC3D_DTYPE).reshape(-1)
+
+
+# ---------------------------------------------------------------- motion estimation
+
+def ulm_stage1_slices(ctx: Context):
+    """The stage-1 reference slices [2][K][F][Nz][Nu] (complex64) that
+    rca_beamform_stage1 leaves in the context's workspace, as a tensor view."""
+    torch = _torch()
+    off = ctypes.c_size_t()
+    _check(_lib.ulm_slices_offset(ctx.handle, ctypes.byref(off)))
+    shape = (2, ctx.c.n_angles, ctx.c.n_frames, ctx.c.nz, ctx.c.nu)
+    n = 8 * int(np.prod(shape))
+    start = ctx.ws_ptr.value - ctx.ws.data_ptr() + off.value
+    return ctx.ws[start:start + n].view(torch.complex64).view(shape)
+
+
+def ulm_motion_workspace_size(ctx: Context, max_lag: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.ulm_motion_workspace_size(ctx.handle, int(max_lag), ctypes.byref(n)))
+    return n.value
+
+
+def ulm_motion_estimate(ctx: Context, slices, ref_frame: int = 0, max_lag: int = 8, disp=None,
+                        motion=None, ws=None, stream=None):
+    """Rigid motion of every frame against `ref_frame` from the stage-1 slices
+    [2][K][F][Nz][Nu] (complex64).  Returns (disp float32 [2][K][F][2] = (dz, du),
+    motion float32 [F][3] = (dx, dy, dz)), in pixels."""
+    torch = _torch()
+    K, F = ctx.c.n_angles, ctx.c.n_frames
+    _require(slices, torch.complex64, (2, K, F, ctx.c.nz, ctx.c.nu), "slices")
+    dev = slices.device
+    if disp is None:
+        disp = torch.empty((2, K, F, 2), dtype=torch.float32, device=dev)
+    if motion is None:
+        motion = torch.empty((F, 3), dtype=torch.float32, device=dev)
+    _require(disp, torch.float32, (2, K, F, 2), "disp")
+    _require(motion, torch.float32, (F, 3), "motion")
+    ws = _ws(ws, ulm_motion_workspace_size(ctx, max_lag), dev)
+    _check(_lib.ulm_motion_estimate(ctx.handle, _ptr(slices), int(ref_frame), int(max_lag),
+                                    _ptr(disp), _ptr(motion), ws.ptr, ws.nbytes, _stream(stream)))
+    return disp, motion
+
+
+# ---------------------------------------------------------------- MB separation
+
+def ulm_separate(ctx: Context, filtered, n_speed: int = 3, subsets=None, stream=None):
+    """Up/down x speed-range subsets of the filtered planes:
+    [2 n_speed][2][B][F][Nz][Nu] complex64 (up ranges first, slowest first)."""
+    torch = _torch()
+    _require(filtered, torch.complex64, ctx.proj_shape, "filtered")
+    shape = (2 * int(n_speed),) + tuple(ctx.proj_shape)
+    if subsets is None:
+        subsets = torch.empty(shape, dtype=torch.complex64, device=filtered.device)
+    _require(subsets, torch.complex64, shape, "subsets")
+    _check(_lib.ulm_separate(ctx.handle, _ptr(filtered), int(n_speed), _ptr(subsets),
+                             _stream(stream)))
+    return subsets

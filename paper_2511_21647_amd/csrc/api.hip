@@ -32,6 +32,13 @@ size_t pair_workspace_bytes(int planes, int F, int capacity);
 hipError_t launch_pairing(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
                           int capacity, ulm_loc3d_t *out, int out_capacity, int *out_count,
                           char *pws, hipStream_t st);
+size_t motion_workspace_bytes(const Geometry &g, int L);
+size_t motion_lds_bytes(const Geometry &g, int L);
+hipError_t launch_motion(const ulm_ctx *ctx, const float2 *S, int ref, int L, float *disp,
+                         float *motion, char *mws, hipStream_t st);
+bool separate_supported(int F);
+hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, float2 *out,
+                           hipStream_t st);
 size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
 hipError_t cnn_images(const float2 *P, const float *fmax, float *x0, int npix, int n0, int nb,
                       hipStream_t st);
@@ -624,5 +631,63 @@ extern "C" int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const 
     HIP_TRY(launch_pairing(ctx, locs, count, capacity, out, out_capacity, out_count, (char *)pws,
                            (hipStream_t)stream),
             "ulm_pair_planes");
+    return ULM_OK;
+}
+
+// ---------------------------------------------------------------- motion estimation
+
+extern "C" int32_t ulm_slices_offset(const ulm_ctx_t *ctx, size_t *offset) {
+    if (!ctx || !offset) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    *offset = ctx->ws.slices;
+    return ULM_OK;
+}
+
+static int32_t check_lag(const ulm_ctx_t *ctx, int32_t max_lag) {
+    const Geometry &g = ctx->geo;
+    if (max_lag < 1 || max_lag > 10) return fail(ULM_ERR_INVALID_ARG, "max_lag must lie in [1, 10]");
+    if (2 * max_lag + 1 > g.nz || 2 * max_lag + 1 > g.nu)
+        return fail(ULM_ERR_INVALID_ARG, "lag window larger than the slice");
+    if (motion_lds_bytes(g, max_lag) == 0)
+        return fail(ULM_ERR_INVALID_ARG, "slice too wide for the motion kernel's LDS band");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_motion_workspace_size(const ulm_ctx_t *ctx, int32_t max_lag, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    const int32_t r = check_lag(ctx, max_lag);
+    if (r != ULM_OK) return r;
+    *bytes = motion_workspace_bytes(ctx->geo, max_lag);
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_motion_estimate(ulm_ctx_t *ctx, const float *slices, int32_t ref_frame,
+                                       int32_t max_lag, float *disp, float *motion, void *mws,
+                                       size_t mws_bytes, void *stream) {
+    if (!ctx || !slices || !disp || !motion || !mws) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    const int32_t r = check_lag(ctx, max_lag);
+    if (r != ULM_OK) return r;
+    if (ref_frame < 0 || ref_frame >= ctx->geo.n_frames)
+        return fail(ULM_ERR_INVALID_ARG, "reference frame outside the ensemble");
+    if (mws_bytes < motion_workspace_bytes(ctx->geo, max_lag))
+        return fail(ULM_ERR_INVALID_ARG, "motion workspace too small");
+    if (((uintptr_t)mws & 255) != 0) return fail(ULM_ERR_INVALID_ARG, "motion workspace not 256-byte aligned");
+    HIP_TRY(launch_motion(ctx, (const float2 *)slices, ref_frame, max_lag, disp, motion, (char *)mws,
+                          (hipStream_t)stream),
+            "ulm_motion_estimate");
+    return ULM_OK;
+}
+
+// ---------------------------------------------------------------- MB separation
+
+extern "C" int32_t ulm_separate(ulm_ctx_t *ctx, const float *filtered, int32_t n_speed,
+                                float *subsets, void *stream) {
+    if (!ctx || !filtered || !subsets) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    if (n_speed < 1 || n_speed > 8) return fail(ULM_ERR_INVALID_ARG, "n_speed must lie in [1, 8]");
+    if (!separate_supported(ctx->geo.n_frames))
+        return fail(ULM_ERR_INVALID_ARG,
+                    "separation needs 2 <= frames <= 512 with no prime factor above 7");
+    HIP_TRY(launch_separate(ctx, (const float2 *)filtered, n_speed, (float2 *)subsets,
+                            (hipStream_t)stream),
+            "ulm_separate");
     return ULM_OK;
 }

@@ -1,0 +1,241 @@
+// MB separation of the filtered planes into flow sub-populations (paper Section
+// II-A5): at every pixel, the F-point DFT of the slow-time signal, an ideal
+// band-pass mask per subset (up = positive-frequency bins 1..H, down = the
+// negative ones, H = (F - 1) / 2, each direction split by |frequency| into S
+// contiguous speed ranges), and the inverse DFT of each masked spectrum.
+//
+// sep_kernel: one work-group per (plane, 16 consecutive pixels).  The frames
+// of those pixels are staged in LDS ([frame][pixel], pixels fastest, so the
+// global loads and stores are 128-byte rows and the butterflies read
+// consecutive banks), transformed by a mixed-radix Stockham FFT (radices 4, 2,
+// 3, 5, 7) that ping-pongs between two LDS buffers, and the spectrum is kept in
+// registers; each subset then rewrites its masked spectrum to LDS, runs the
+// inverse transform and streams the result out.  HBM traffic is one read of
+// the planes and one write per subset.
+#include "common.h"
+
+#include <math.h>
+
+namespace ulm {
+
+constexpr int kSepPix = 16;                 // pixels per work-group
+constexpr int kSepThreads = 256;
+constexpr int kSepMaxFrames = 512;
+constexpr int kSepMaxPass = 12;
+constexpr int kSepMaxSub = 16;              // 2 S subsets, S <= 8
+constexpr int kSepRegs = (kSepMaxFrames * kSepPix + kSepThreads - 1) / kSepThreads;
+
+struct SepArgs {
+    int F, npix, planes, n_sub, H;
+    int n_pass;
+    int radix[kSepMaxPass];
+    int tw_off[kSepMaxPass];                // offset of each pass's twiddles in the table
+    int n_tw;                               // twiddle entries (all passes)
+    int lo[kSepMaxSub], hi[kSepMaxSub];     // |k| range of each subset
+};
+
+__device__ inline float2 cmulf(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cmulf_conj(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// One Stockham pass of radix R over every pixel: x -> y.  p = product of the
+// radices of the earlier passes; tw[k R + q] = exp(-2 pi i q k / (p R)) for
+// k < p; wr[q] = exp(-2 pi i q / R).  INV uses the conjugates.
+template <int R, bool INV>
+__device__ void sep_pass(const float2 *__restrict__ x, float2 *__restrict__ y, int F, int p,
+                         const float2 *tw, const float2 *wr)
+{
+    const int nb = F / R;                                  // butterflies per pixel
+    for (int e = threadIdx.x; e < nb * kSepPix; e += kSepThreads) {
+        const int i = e / kSepPix, px = e % kSepPix;
+        const int k = i % p;
+        float2 u[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 v = x[(i + q * nb) * kSepPix + px];
+            if (q > 0) v = INV ? cmulf_conj(v, tw[k * R + q]) : cmulf(v, tw[k * R + q]);
+            u[q] = v;
+        }
+        const int j = (i - k) * R + k;
+#pragma unroll
+        for (int qo = 0; qo < R; ++qo) {
+            float2 s = u[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                const float2 w = wr[(q * qo) % R];
+                const float2 t = INV ? cmulf_conj(u[q], w) : cmulf(u[q], w);
+                s.x += t.x;
+                s.y += t.y;
+            }
+            y[(j + qo * p) * kSepPix + px] = s;
+        }
+    }
+}
+
+// All passes; returns the buffer that holds the result.
+template <bool INV>
+__device__ float2 *sep_fft(float2 *a, float2 *b, const SepArgs &g, const float2 *tw,
+                           const float2 *wr)
+{
+    int p = 1;
+    for (int s = 0; s < g.n_pass; ++s) {
+        const int R = g.radix[s];
+        const float2 *t = tw + g.tw_off[s];
+        switch (R) {
+            case 2: sep_pass<2, INV>(a, b, g.F, p, t, wr + 0); break;
+            case 3: sep_pass<3, INV>(a, b, g.F, p, t, wr + 2); break;
+            case 4: sep_pass<4, INV>(a, b, g.F, p, t, wr + 5); break;
+            case 5: sep_pass<5, INV>(a, b, g.F, p, t, wr + 9); break;
+            default: sep_pass<7, INV>(a, b, g.F, p, t, wr + 14); break;
+        }
+        __syncthreads();
+        float2 *c = a;
+        a = b;
+        b = c;
+        p *= R;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(kSepThreads) void sep_kernel(const float2 *__restrict__ P,
+                                                          float2 *__restrict__ out, SepArgs g)
+{
+    extern __shared__ float2 sm[];
+    float2 *buf0 = sm;                                     // [F][kSepPix]
+    float2 *buf1 = sm + (size_t)g.F * kSepPix;
+    float2 *tw = buf1 + (size_t)g.F * kSepPix;             // [n_tw]
+    float2 *wr = tw + g.n_tw;                              // radix roots: 2, 3, 4, 5, 7 -> 21
+    const int groups = cdiv(g.npix, kSepPix);
+    const int plane = blockIdx.x / groups, px0 = (blockIdx.x % groups) * kSepPix;
+    const int t = threadIdx.x;
+
+    // twiddles of every pass and the roots of unity of every radix (FP64 -> FP32)
+    {
+        int p = 1;
+        for (int s = 0; s < g.n_pass; ++s) {
+            const int R = g.radix[s];
+            for (int e = t; e < p * R; e += kSepThreads) {
+                const int k = e / R, q = e % R;
+                double sn, cs;
+                sincospi(-2.0 * q * k / (double)(p * R), &sn, &cs);
+                tw[g.tw_off[s] + e] = make_float2((float)cs, (float)sn);
+            }
+            p *= R;
+        }
+        const int base[5] = {0, 2, 5, 9, 14}, rad[5] = {2, 3, 4, 5, 7};
+        for (int e = t; e < 21; e += kSepThreads) {
+            int r = 0;
+            while (r < 4 && e >= base[r + 1]) ++r;
+            const int q = e - base[r];
+            double sn, cs;
+            sincospi(-2.0 * q / (double)rad[r], &sn, &cs);
+            wr[e] = make_float2((float)cs, (float)sn);
+        }
+    }
+    const float2 *src = P + (size_t)plane * g.F * g.npix + px0;
+    const int npx = min(kSepPix, g.npix - px0);
+    for (int e = t; e < g.F * kSepPix; e += kSepThreads) {
+        const int f = e / kSepPix, px = e % kSepPix;
+        buf0[e] = px < npx ? src[(size_t)f * g.npix + px] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const float2 *X = sep_fft<false>(buf0, buf1, g, tw, wr);
+    // the spectrum stays in registers: element e = t + 256 r
+    float2 xr[kSepRegs];
+    int nreg = 0;
+#pragma unroll
+    for (int r = 0; r < kSepRegs; ++r) {
+        const int e = t + r * kSepThreads;
+        if (e < g.F * kSepPix) {
+            xr[r] = X[e];
+            nreg = r + 1;
+        }
+    }
+    const float scale = 1.0f / (float)g.F;
+    const size_t sub_stride = (size_t)g.planes * g.F * g.npix;
+    for (int s = 0; s < g.n_sub; ++s) {
+        const bool up = s < g.n_sub / 2;
+        const int lo = g.lo[s], hi = g.hi[s];
+        __syncthreads();                                    // previous subset's reads done
+#pragma unroll
+        for (int r = 0; r < kSepRegs; ++r) {
+            if (r < nreg) {
+                const int e = t + r * kSepThreads;
+                if (e < g.F * kSepPix) {
+                    const int k = e / kSepPix;
+                    const int m = up ? k : g.F - k;
+                    const bool keep = (up ? (k >= 1 && k <= g.H) : (k >= g.F - g.H)) && m >= lo && m < hi;
+                    buf0[e] = keep ? xr[r] : make_float2(0.f, 0.f);
+                }
+            }
+        }
+        __syncthreads();
+        const float2 *Y = sep_fft<true>(buf0, buf1, g, tw, wr);
+        float2 *dst = out + s * sub_stride + (size_t)plane * g.F * g.npix + px0;
+        for (int e = t; e < g.F * kSepPix; e += kSepThreads) {
+            const int f = e / kSepPix, px = e % kSepPix;
+            if (px < npx) {
+                const float2 v = Y[e];
+                dst[(size_t)f * g.npix + px] = make_float2(v.x * scale, v.y * scale);
+            }
+        }
+    }
+}
+
+// Radices for F (4 first, then 2, 3, 5, 7); false if F has another prime factor.
+static bool sep_factor(int F, SepArgs &g) {
+    g.n_pass = 0;
+    int n = F, off = 0, p = 1;
+    const int order[5] = {4, 2, 3, 5, 7};
+    for (int r : order) {
+        while (n % r == 0) {
+            if (g.n_pass == kSepMaxPass) return false;
+            g.radix[g.n_pass] = r;
+            g.tw_off[g.n_pass] = off;
+            off += p * r;
+            p *= r;
+            ++g.n_pass;
+            n /= r;
+        }
+    }
+    g.n_tw = off;
+    return n == 1;
+}
+
+bool separate_supported(int F) {
+    SepArgs g;
+    return F >= 2 && F <= kSepMaxFrames && sep_factor(F, g);
+}
+
+size_t separate_lds_bytes(int F) {
+    SepArgs g;
+    sep_factor(F, g);
+    return sizeof(float2) * ((size_t)2 * F * kSepPix + g.n_tw + 21);
+}
+
+hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, float2 *out,
+                           hipStream_t st)
+{
+    const Geometry &geo = ctx->geo;
+    SepArgs g;
+    if (!sep_factor(geo.n_frames, g)) return hipErrorInvalidValue;
+    g.F = geo.n_frames;
+    g.npix = geo.nz * geo.nu;
+    g.planes = geo.n_planes;
+    g.n_sub = 2 * n_speed;
+    g.H = (g.F - 1) / 2;
+    for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < n_speed; ++s) {
+            g.lo[d * n_speed + s] = 1 + (s * g.H) / n_speed;
+            g.hi[d * n_speed + s] = 1 + ((s + 1) * g.H) / n_speed;
+        }
+    const int groups = cdiv(g.npix, kSepPix);
+    hipLaunchKernelGGL(sep_kernel, dim3(groups * g.planes), dim3(kSepThreads),
+                       separate_lds_bytes(g.F), st, P, out, g);
+    return hipGetLastError();
+}
+
+}  // namespace ulm

@@ -64,3 +64,22 @@ def gaussian_spots(nz: int, nu: int, n_spots: int, sigma: float, seed: int, spac
     for cz, cu in centres:
         img += np.exp(-((zz - cz) ** 2 + (uu - cu) ** 2) / (2 * sigma ** 2))
     return img, centres
+
+
+def speckle_field(nz: int, nu: int, seed: int, smooth: float = 1.5) -> np.ndarray:
+    """Band-limited complex Gaussian field [nz][nu] (complex128): a speckle
+    pattern whose envelope has a correlation length of a few pixels."""
+    g = rng(seed)
+    x = g.standard_normal((nz, nu)) + 1j * g.standard_normal((nz, nu))
+    kz = np.fft.fftfreq(nz)[:, None]
+    ku = np.fft.fftfreq(nu)[None, :]
+    return np.fft.ifft2(np.fft.fft2(x) * np.exp(-2 * (np.pi * smooth) ** 2 * (kz ** 2 + ku ** 2)))
+
+
+def shift_field(field: np.ndarray, dz: float, du: float) -> np.ndarray:
+    """`field` moved by (dz, du) pixels, circularly, by a Fourier phase ramp
+    (exact for a band-limited field): out(p) = field(p - d)."""
+    nz, nu = field.shape
+    kz = np.fft.fftfreq(nz)[:, None]
+    ku = np.fft.fftfreq(nu)[None, :]
+    return np.fft.ifft2(np.fft.fft2(field) * np.exp(-2j * np.pi * (kz * dz + ku * du)))

@@ -191,6 +191,41 @@ def time_motion(cfg, ctx, args):
                          "algorithmic_flops": flops}}
 
 
+SEPARATION_SPEEDS = 3
+
+
+def time_separation(cfg, ctx, args):
+    """MB separation of a 2 x 250 x 274 x 300 plane stack into up/down x 3 speed
+    ranges (six subsets): ms per ensemble and the HBM rate of its algorithmic
+    traffic (one read of the planes, one write per subset)."""
+    import torch
+    import paper_2511_21647_amd as ulm
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    planes = torch.randn(ctx.proj_shape, dtype=torch.complex64, device="cuda", generator=g)
+    subs = torch.empty((2 * SEPARATION_SPEEDS,) + tuple(ctx.proj_shape), dtype=torch.complex64,
+                       device="cuda")
+    for _ in range(args.warmup):
+        ulm.ulm_separate(ctx, planes, SEPARATION_SPEEDS, subs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        ulm.ulm_separate(ctx, planes, SEPARATION_SPEEDS, subs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    nbytes = planes.numel() * 8 * (1 + 2 * SEPARATION_SPEEDS)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    del planes, subs
+    torch.cuda.empty_cache()
+    return {"ms_per_ensemble": round(ms, 3), "subsets": 2 * SEPARATION_SPEEDS,
+            "roofline": {"bound": "hbm", "kernel": "sep_kernel", "achieved": round(gbs, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes": nbytes}}
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -205,6 +240,8 @@ def run_gpu(args):
     log(f"plain: {ms:.2f} ms/ensemble {stage}")
     forms["plain"]["motion_estimation"] = time_motion(cfg, ctx, args)
     log(f"motion estimation: {forms['plain']['motion_estimation']}")
+    forms["plain"]["mb_separation"] = time_separation(cfg, ctx, args)
+    log(f"MB separation: {forms['plain']['mb_separation']}")
     if args.form == "both" and os.path.exists(WEIGHTS):
         ctx_b = ulm.Context(cfg, precision=ulm.ULM_PREC_BF16X3)
         params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()

@@ -261,6 +261,23 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
         }
     }
     if (max_taps > kFirMaxTaps) return fail(ULM_ERR_INVALID_ARG, "stage-2 shift needs too many taps");
+    // stage 2 runs kFirGroup slabs per work-group from one slice tile when the
+    // union of their tap ranges fits the tile's halo
+    int fir_group = 1;
+    if (c.n_blocks >= kFirGroup) {
+        int gspan = 0;
+        for (int k = 0; k < c.n_angles; ++k)
+            for (int b0 = 0; b0 < c.n_blocks; b0 += kFirGroup) {
+                int lo = INT32_MAX, hi = INT32_MIN;
+                for (int b = b0; b < std::min(b0 + kFirGroup, c.n_blocks); ++b) {
+                    const int2 m = meta[k * c.n_blocks + b];
+                    lo = std::min(lo, m.x);
+                    hi = std::max(hi, m.x + m.y);
+                }
+                gspan = std::max(gspan, hi - lo);
+            }
+        if (gspan <= kFirMaxTaps) fir_group = kFirGroup;
+    }
     std::vector<float2> taps((size_t)c.n_angles * c.n_blocks * max_taps, make_float2(0.f, 0.f));
     for (int kb = 0; kb < c.n_angles * c.n_blocks; ++kb)
         for (int q = 0; q < meta[kb].y; ++q) {
@@ -289,6 +306,7 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
     g.u0 = (float)c.u0;
     g.z0 = (float)c.z0;
     ctx->tab.n_taps = max_taps;
+    ctx->tab.fir_group = fir_group;
     layout_workspace(ctx);
 
     ctx->tab.das_len = das_len;

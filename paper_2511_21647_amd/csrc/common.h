@@ -16,6 +16,7 @@ constexpr int kDasFrames = 16;     // frames beamformed per delay evaluation
 constexpr int kFirTileZ = 32;
 constexpr int kFirTileU = 64;
 constexpr int kFirMaxTaps = 48;
+constexpr int kFirGroup = 4;       // slabs per stage-2 work-group (many-slab projections)
 
 constexpr int kGramBlock = 64;     // frames per Gram block (rows and columns)
 constexpr int kGramChunk = 2048;   // pixels reduced by one Gram work-group
@@ -49,6 +50,7 @@ struct Tables {
     int2 *tap_meta;    // [K][B]    (first tap offset, number of taps)
     double *angles;    // [K]       steering angles (simulator)
     int n_taps;        // maximum taps over (transmit, block)
+    int fir_group;     // slabs per stage-2 work-group: 1 or kFirGroup
 };
 
 // Offsets of the workspace regions, in bytes.

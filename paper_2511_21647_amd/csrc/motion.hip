@@ -116,20 +116,24 @@ __global__ __launch_bounds__(256) void mot_corr_kernel(const float2 *__restrict_
         uu = uu < 0 ? uu + a.nu : (uu >= a.nu ? uu - a.nu : uu);
         Bs[e] = bs[(size_t)zz * a.nu + uu];
     }
-    // this lane's lag in every tile, as an LDS offset
-    int off[NT];
+    // wave w: lag tiles of half w / 2 (NH of the NT tiles), pixels of half w % 2
+    // of every staged step; the two waves of a tile half are summed at the end
+    constexpr int NH = (NT + 1) / 2;
+    const int th = wave >> 1, ph = wave & 1;
+    int off[NH];
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-        const int j = tt * 32 + i32;
+    for (int tt = 0; tt < NH; ++tt) {
+        const int j = (th * NH + tt) * 32 + i32;
         off[tt] = 0;
         if (j < a.NL) {
             const int dz = j / (2 * L + 1) - L, du = j % (2 * L + 1) - L;
             off[tt] = dz * W2 + du;
         }
     }
-    f32x16 acc[NT];
+    const int nt_here = min(NH, NT - th * NH);          // tiles of this half (odd NT)
+    f32x16 acc[NH];
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) acc[tt] = f32x16{};
+    for (int tt = 0; tt < NH; ++tt) acc[tt] = f32x16{};
     double d1 = 0.0, d2 = 0.0;
 
     const int npx = rows * a.nu;
@@ -163,31 +167,36 @@ __global__ __launch_bounds__(256) void mot_corr_kernel(const float2 *__restrict_
             d1 += s1;
             d2 += s2;
         }
-        // wave w contracts pixels p0 + 64 w .. p0 + 64 w + 63, two per MFMA
-        for (int st = 0; st < 32; ++st) {
-            const int pl = wave * 64 + 2 * st + hk;
+        // pixels p0 + 128 ph .. p0 + 128 ph + 127, two per MFMA
+#pragma unroll 2
+        for (int st = 0; st < 64; ++st) {
+            const int pl = ph * 128 + 2 * st + hk;
             const float av = As[i32 * kMotAS + pl];
             const int pp = min(p0 + pl, npx - 1);
             const int pz = pp / a.nu, pu = pp - pz * a.nu;
             const int base = (pz + L) * W2 + pu + L;
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt)
-                acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Bs[base - off[tt]], acc[tt], 0, 0, 0);
+            for (int tt = 0; tt < NH; ++tt)
+                if (tt < nt_here)
+                    acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Bs[base - off[tt]], acc[tt], 0, 0, 0);
         }
     }
-    // sum the four waves' accumulators in a fixed order, in LDS
+    // sum the two waves of each tile half in a fixed order, in LDS
     float *Red = smem;                                  // [NT][32 frames][32 lags]
     __syncthreads();
-    for (int wv = 0; wv < 4; ++wv) {
-        if (wave == wv) {
+    for (int round = 0; round < 2; ++round) {
+        if (ph == round) {
 #pragma unroll
-            for (int tt = 0; tt < NT; ++tt)
+            for (int tt = 0; tt < NH; ++tt) {
+                if (tt >= nt_here) continue;
+                const int tg = th * NH + tt;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int r = 8 * (q >> 2) + 4 * hk + (q & 3);
-                    float *d = &Red[(tt * 32 + r) * 32 + i32];
-                    *d = wv == 0 ? acc[tt][q] : *d + acc[tt][q];
+                    float *d = &Red[(tg * 32 + r) * 32 + i32];
+                    *d = round == 0 ? acc[tt][q] : *d + acc[tt][q];
                 }
+            }
         }
         __syncthreads();
     }

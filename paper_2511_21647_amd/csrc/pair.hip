@@ -8,13 +8,17 @@
 // y lies in slab b, and their x must lie in the YZ record's slab.
 //
 //   pair_bounds_kernel  record range of every (plane, frame) in the sorted list
-//   pair_best_kernel    every record's best candidate (one work-group per frame)
-//   pair_count_kernel   mutual pairs per frame
-//   launch_scan         frame offsets (the localisers' scan)
-//   pair_write_kernel   the pairs of each frame in XZ record order
+//   pair_best_kernel    every record's best candidate (one work-group per
+//                       (frame, plane))
+//   pair_count_kernel   mutual pairs per (frame, XZ plane)
+//   launch_scan         their offsets, XZ planes fastest (the localisers' scan)
+//   pair_write_kernel   the pairs of each (frame, XZ plane); records are sorted by
+//                       plane, so (frame, plane) order is (frame, XZ index) order
 #include "common.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace ulm {
 
@@ -24,7 +28,7 @@ struct PairArgs {
     int F, B, per;          // frames, slabs per orientation, slab width in pixels
     const int *bounds;      // [2B][F][2]
     int *best;              // [n]
-    int *cnt, *off;         // [F]
+    int *cnt, *off;         // [F][B]
 };
 
 // slab of a plane coordinate (pixel units), or -1 outside [-0.5, 1e6)
@@ -68,97 +72,90 @@ __device__ inline float pair_cost(const ulm_loc_t &a, const ulm_loc_t &b, int B,
 
 __global__ __launch_bounds__(256) void pair_best_kernel(PairArgs a)
 {
-    const int f = blockIdx.x;
-    // every record of this frame, XZ planes first
-    for (int p = 0; p < 2 * a.B; ++p) {
-        const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
-        for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-            const ulm_loc_t me = a.locs[r];
-            const bool xz = p < a.B;
-            // the other orientation's segment that can hold my partner
-            int q;
-            if (a.B == 1) {
-                q = xz ? 1 : 0;
-            } else {
-                const int sl = slab_of(me.u, a.per);
-                if (sl < 0 || sl >= a.B) {       // outside every slab: no partner
-                    a.best[r] = -1;
-                    continue;
-                }
-                q = xz ? a.B + sl : sl;
+    const int f = blockIdx.x, p = blockIdx.y;
+    const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
+    const bool xz = p < a.B;
+    for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+        const ulm_loc_t me = a.locs[r];
+        // the other orientation's segment that can hold my partner
+        int q;
+        if (a.B == 1) {
+            q = xz ? 1 : 0;
+        } else {
+            const int sl = slab_of(me.u, a.per);
+            if (sl < 0 || sl >= a.B) {       // outside every slab: no partner
+                a.best[r] = -1;
+                continue;
             }
-            const int clo = a.bounds[2 * (q * a.F + f)], chi = a.bounds[2 * (q * a.F + f) + 1];
-            float bc = INFINITY;
-            int bi = -1;
-            for (int c = clo; c < chi; ++c) {
-                const ulm_loc_t o = a.locs[c];
-                const float cost = xz ? pair_cost(me, o, a.B, a.per) : pair_cost(o, me, a.B, a.per);
-                if (cost < bc) {            // strict: the first (smallest index) minimum wins
-                    bc = cost;
-                    bi = c;
-                }
-            }
-            a.best[r] = bi;
+            q = xz ? a.B + sl : sl;
         }
+        const int clo = a.bounds[2 * (q * a.F + f)], chi = a.bounds[2 * (q * a.F + f) + 1];
+        float bc = INFINITY;
+        int bi = -1;
+        for (int c = clo; c < chi; ++c) {
+            const ulm_loc_t o = a.locs[c];
+            const float cost = xz ? pair_cost(me, o, a.B, a.per) : pair_cost(o, me, a.B, a.per);
+            if (cost < bc) {            // strict: the first (smallest index) minimum wins
+                bc = cost;
+                bi = c;
+            }
+        }
+        a.best[r] = bi;
     }
 }
 
 __global__ __launch_bounds__(256) void pair_count_kernel(PairArgs a)
 {
-    const int f = blockIdx.x;
+    const int f = blockIdx.x, p = blockIdx.y;
+    const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
     int c = 0;
-    for (int p = 0; p < a.B; ++p) {
-        const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
-        for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-            const int j = a.best[r];
-            c += (j >= 0 && a.best[j] == r) ? 1 : 0;
-        }
+    for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+        const int j = a.best[r];
+        c += (j >= 0 && a.best[j] == r) ? 1 : 0;
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     __shared__ int red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
     __syncthreads();
-    if (threadIdx.x == 0) a.cnt[f] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) a.cnt[f * a.B + p] = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ __launch_bounds__(256) void pair_write_kernel(PairArgs a, ulm_loc3d_t *__restrict__ out,
                                                          int out_capacity)
 {
-    const int f = blockIdx.x;
+    const int f = blockIdx.x, p = blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __shared__ int wave_tot[4];
-    int base = a.off[f];
-    for (int p = 0; p < a.B; ++p) {
-        const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
-        for (int r0 = lo; r0 < hi; r0 += blockDim.x) {
-            const int r = r0 + threadIdx.x;
-            int j = -1;
-            if (r < hi) {
-                j = a.best[r];
-                if (j >= 0 && a.best[j] != r) j = -1;
-            }
-            const bool take = j >= 0;
-            const unsigned long long bal = __ballot(take);
-            if (lane == 0) wave_tot[wv] = __popcll(bal);
-            __syncthreads();
-            int o = base + __popcll(bal & ((1ull << lane) - 1ull));
-            for (int q = 0; q < wv; ++q) o += wave_tot[q];
-            if (take && o < out_capacity) {
-                const ulm_loc_t xa = a.locs[r], yb = a.locs[j];
-                ulm_loc3d_t v;
-                v.frame = f;
-                v.x = xa.u;
-                v.y = yb.u;
-                v.z = (xa.z + yb.z) * 0.5f;
-                v.i_xz = xa.intensity;
-                v.i_yz = yb.intensity;
-                v.idx_xz = r;
-                v.idx_yz = j;
-                out[o] = v;
-            }
-            base += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-            __syncthreads();
+    int base = a.off[f * a.B + p];
+    const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
+    for (int r0 = lo; r0 < hi; r0 += blockDim.x) {
+        const int r = r0 + threadIdx.x;
+        int j = -1;
+        if (r < hi) {
+            j = a.best[r];
+            if (j >= 0 && a.best[j] != r) j = -1;
         }
+        const bool take = j >= 0;
+        const unsigned long long bal = __ballot(take);
+        if (lane == 0) wave_tot[wv] = __popcll(bal);
+        __syncthreads();
+        int o = base + __popcll(bal & ((1ull << lane) - 1ull));
+        for (int q = 0; q < wv; ++q) o += wave_tot[q];
+        if (take && o < out_capacity) {
+            const ulm_loc_t xa = a.locs[r], yb = a.locs[j];
+            ulm_loc3d_t v;
+            v.frame = f;
+            v.x = xa.u;
+            v.y = yb.u;
+            v.z = (xa.z + yb.z) * 0.5f;
+            v.i_xz = xa.intensity;
+            v.i_yz = yb.intensity;
+            v.idx_xz = r;
+            v.idx_yz = j;
+            out[o] = v;
+        }
+        base += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        __syncthreads();
     }
 }
 
@@ -167,7 +164,7 @@ hipError_t launch_scan(const int *cnt, int *off, int n, int *count, hipStream_t 
 size_t pair_workspace_bytes(int planes, int F, int capacity) {
     auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return a256(sizeof(int) * 2 * (size_t)planes * F) + a256(sizeof(int) * (size_t)capacity) +
-           2 * a256(sizeof(int) * (size_t)F);
+           2 * a256(sizeof(int) * (size_t)F * (planes / 2));
 }
 
 hipError_t launch_pairing(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *count,
@@ -179,8 +176,9 @@ hipError_t launch_pairing(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *
     const int planes = g.n_planes, F = g.n_frames;
     int *bounds = (int *)pws;
     int *best = (int *)(pws + a256(sizeof(int) * 2 * (size_t)planes * F));
-    int *cnt = (int *)((char *)best + a256(sizeof(int) * (size_t)capacity));
-    int *off = (int *)((char *)cnt + a256(sizeof(int) * (size_t)F));
+    const int B = g.n_blocks;
+    int *cnt = (int *)((char *)best + a256(sizeof(int) * (size_t)std::max(capacity, 1)));
+    int *off = (int *)((char *)cnt + a256(sizeof(int) * (size_t)F * B));
     const int nkeys = planes * F;
     hipLaunchKernelGGL(pair_bounds_kernel, dim3(cdiv(nkeys, 256)), dim3(256), 0, st, locs, count,
                        capacity, nkeys, F, bounds);
@@ -194,11 +192,11 @@ hipError_t launch_pairing(const ulm_ctx *ctx, const ulm_loc_t *locs, const int *
     a.best = best;
     a.cnt = cnt;
     a.off = off;
-    hipLaunchKernelGGL(pair_best_kernel, dim3(F), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(pair_count_kernel, dim3(F), dim3(256), 0, st, a);
-    hipError_t e = launch_scan(cnt, off, F, out_count, st);
+    hipLaunchKernelGGL(pair_best_kernel, dim3(F, planes), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(pair_count_kernel, dim3(F, B), dim3(256), 0, st, a);
+    hipError_t e = launch_scan(cnt, off, F * B, out_count, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pair_write_kernel, dim3(F), dim3(256), 0, st, a, out, out_capacity);
+    hipLaunchKernelGGL(pair_write_kernel, dim3(F, B), dim3(256), 0, st, a, out, out_capacity);
     return hipGetLastError();
 }
 

@@ -22,6 +22,14 @@ namespace ulm {
 // element) window start win[...] exactly.
 // LDS holds, per staged sample, (IQ[s], IQ[s+1] - IQ[s]) so the interpolation
 // is two FMAs per frame.
+// LDS slot of staged sample n: the low two bits are XORed with bits 4-5, so the
+// 16 lanes that store entries 4 r + i together (r = 0..15) hit 16 different
+// 16-byte bank groups, while consecutive entries still map to distinct slots.
+// (Interleaving frames across lanes instead keeps the reads' bank pattern but
+// scatters each lane quad's global loads over four frames, which measured
+// slower.)
+__device__ inline int das_slot(int n) { return n ^ ((n >> 4) & 3); }
+
 template <int FB, int LEN>
 __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     const float2 *__restrict__ iq, float2 *__restrict__ S, const float *__restrict__ stz,
@@ -99,7 +107,7 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
             const int e = t + q * kDasThreads;
             const int fl = e / RUNS, run = e % RUNS;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) buf[b][fl][4 * run + i] = st[q][i];
+            for (int i = 0; i < 4; ++i) buf[b][fl][das_slot(4 * run + i)] = st[q][i];
         }
     };
 
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
         const float s = crx + stz_p;
         const float fl = floorf(s);
         const float fr = s - fl;
-        const int idx = min(max((int)fl + sti_p - s_lo, 0), LEN - 1);
+        const int idx = das_slot(min(max((int)fl + sti_p - s_lo, 0), LEN - 1));
         // four LDS reads in flight: frame f + 4 is requested while frame f is applied
         float4 vq[4];
 #pragma unroll

@@ -68,10 +68,12 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     constexpr int RUNS = LEN / 4;
     constexpr int NQ = FB * RUNS / kDasThreads;
     static_assert(NQ >= 1 && FB * RUNS % kDasThreads == 0, "staging map");
-    float4 st[NQ][4];
-    float prx;
-    float2 pph;
-    auto load = [&](int j) {
+    // two register sets: the global loads of element j + 2 are in flight while
+    // element j is applied and element j + 1 (loaded one step earlier) is stored
+    float4 sa[NQ][4], sb[NQ][4];
+    float pa, pb;
+    float2 qa, qb;
+    auto load = [&](int j, float4 (&st)[NQ][4], float &prx, float2 &pph) {
         const int s_lo = wj[j];
         const float2 *ch = blk + (size_t)j * g.n_samp;
 #pragma unroll
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
         prx = rxd[(size_t)j * npix + pix];
         pph = rxp[(size_t)j * npix + pix];
     };
-    auto store = [&](int b) {
+    auto store = [&](int b, const float4 (&st)[NQ][4]) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
@@ -114,20 +116,7 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     float2 acc[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) acc[f] = make_float2(0.f, 0.f);
-
-    load(0);
-    store(0);
-    float crx = prx;
-    float2 cph = pph;
-    int s_lo = wj[0];
-    __syncthreads();
-
-    for (int j = 0; j < g.n_elem; ++j) {
-        const int cur = j & 1;
-        // the last iteration re-stages the last element into the idle buffer, so
-        // the loop body has no branch around the stores
-        const int jn = min(j + 1, g.n_elem - 1);
-        load(jn);
+    auto apply = [&](int cur, float crx, float2 cph, int s_lo) {
         const float s = crx + stz_p;
         const float fl = floorf(s);
         const float fr = s - fl;
@@ -145,12 +134,37 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
             acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));
             acc[f].y = fmaf(cph.x, xi, fmaf(cph.y, xr, acc[f].y));
         }
+    };
 
-        store(cur ^ 1);
-        crx = prx;
-        cph = pph;
-        s_lo = wj[jn];
+    const int n = g.n_elem, last = n - 1;
+    load(0, sa, pa, qa);
+    store(0, sa);
+    float crx = pa;
+    float2 cph = qa;
+    int s_lo = wj[0];
+    load(min(1, last), sb, pb, qb);
+    __syncthreads();
+    // the last steps re-stage the last element into the idle buffer, so the
+    // loop body has no branch around the stores
+    for (int j = 0; j < n; j += 2) {
+        // buf[0] holds element j, sb element j + 1
+        load(min(j + 2, last), sa, pa, qa);
+        apply(0, crx, cph, s_lo);
+        store(1, sb);
+        crx = pb;
+        cph = qb;
+        s_lo = wj[min(j + 1, last)];
         __syncthreads();
+        if (j + 1 < n) {
+            // buf[1] holds element j + 1, sa element j + 2
+            load(min(j + 3, last), sb, pb, qb);
+            apply(1, crx, cph, s_lo);
+            store(0, sa);
+            crx = pa;
+            cph = qa;
+            s_lo = wj[min(j + 2, last)];
+            __syncthreads();
+        }
     }
 
     if (!valid) return;

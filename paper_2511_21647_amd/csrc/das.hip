@@ -22,13 +22,17 @@ namespace ulm {
 // element) window start win[...] exactly.
 // LDS holds, per staged sample, (IQ[s], IQ[s+1] - IQ[s]) so the interpolation
 // is two FMAs per frame.
-// LDS slot of staged sample n: the low two bits are XORed with bits 4-5, so the
-// 16 lanes that store entries 4 r + i together (r = 0..15) hit 16 different
-// 16-byte bank groups, while consecutive entries still map to distinct slots.
-// (Interleaving frames across lanes instead keeps the reads' bank pattern but
-// scatters each lane quad's global loads over four frames, which measured
-// slower.)
-__device__ inline int das_slot(int n) { return n ^ ((n >> 4) & 3); }
+// Staging map and LDS slots.  Thread e stages run `run` (samples 4 run ..
+// 4 run + 3 and their differences) of frame `fl`:
+//   fl  = 4 (e / 4R) + (e / 4) % 4,   run = e % 4 + 4 ((e % 4R) / 16),   R = runs per frame,
+// so each lane quad loads 4 consecutive runs of one frame (one 128-byte span).
+// LDS serves 128 bytes (8 lanes of a 16-byte access) per clock; entry n of
+// frame f sits in slot n ^ (2 (f % 2) + (n / 8) % 2), which gives the 8 stores
+// of two quads 8 different 16-byte bank groups and keeps consecutive entries
+// of a frame in different bank groups for the reads.
+__device__ inline int das_slot(int f, int n) { return n ^ ((2 * (f & 1) + ((n >> 3) & 1)) & 3); }
+template <int RUNS> __device__ inline int das_frame(int e) { return 4 * (e / (4 * RUNS)) + ((e >> 2) & 3); }
+template <int RUNS> __device__ inline int das_run(int e) { return (e & 3) + 4 * ((e % (4 * RUNS)) >> 4); }
 
 template <int FB, int LEN>
 __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
@@ -76,23 +80,27 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     auto load = [&](int j, float4 (&st)[NQ][4], float &prx, float2 &pph) {
         const int s_lo = wj[j];
         const float2 *ch = blk + (size_t)j * g.n_samp;
+        // the whole window (and the sample after it) inside the record: the same
+        // answer for every thread, so the branch below does not diverge
+        const bool inside = s_lo >= 0 && s_lo + LEN < g.n_samp;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
-            const int fl = e / RUNS, run = e % RUNS;
+            const int fl = das_frame<RUNS>(e), run = das_run<RUNS>(e);
             const int f = f0 + fl;
             const float2 *row = ch + (size_t)min(f, g.n_frames - 1) * frame_stride;
             const int gs = s_lo + 4 * run;
             float2 x[5];
-            if (gs >= 0 && gs + 4 < g.n_samp) {
+            if (inside) {
 #pragma unroll
                 for (int i = 0; i < 5; ++i) x[i] = row[gs + i];
             } else {
 #pragma unroll
                 for (int i = 0; i < 5; ++i) {
                     const int gi = gs + i;
-                    x[i] = (gi >= 0 && gi < g.n_samp) ? row[min(max(gi, 0), g.n_samp - 1)]
-                                                      : make_float2(0.f, 0.f);
+                    const float2 v = row[min(max(gi, 0), g.n_samp - 1)];
+                    const bool ok = gi >= 0 && gi < g.n_samp;
+                    x[i] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);
                 }
             }
             // frames past the end read the last frame; their sums are never written
@@ -107,9 +115,9 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
-            const int fl = e / RUNS, run = e % RUNS;
+            const int fl = das_frame<RUNS>(e), run = das_run<RUNS>(e);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) buf[b][fl][das_slot(4 * run + i)] = st[q][i];
+            for (int i = 0; i < 4; ++i) buf[b][fl][das_slot(fl, 4 * run + i)] = st[q][i];
         }
     };
 
@@ -120,15 +128,15 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
         const float s = crx + stz_p;
         const float fl = floorf(s);
         const float fr = s - fl;
-        const int idx = das_slot(min(max((int)fl + sti_p - s_lo, 0), LEN - 1));
+        const int idx = min(max((int)fl + sti_p - s_lo, 0), LEN - 1);
         // four LDS reads in flight: frame f + 4 is requested while frame f is applied
         float4 vq[4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) vq[f] = buf[cur][f][idx];
+        for (int f = 0; f < 4; ++f) vq[f] = buf[cur][f][das_slot(f, idx)];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
             const float4 v = vq[f & 3];
-            if (f + 4 < FB) vq[f & 3] = buf[cur][f + 4][idx];
+            if (f + 4 < FB) vq[f & 3] = buf[cur][f + 4][das_slot(f + 4, idx)];
             const float xr = fmaf(fr, v.z, v.x);
             const float xi = fmaf(fr, v.w, v.y);
             acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));

@@ -41,6 +41,73 @@ __device__ inline float2 cmulf_conj(float2 a, float2 b) {   // a * conj(b)
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
+// -i z (forward) or +i z (inverse)
+template <bool INV>
+__device__ inline float2 mul_mi(float2 z) { return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x); }
+
+// In-place R-point DFT of u, u_out[m] = sum_q u[q] exp(-+2 pi i q m / R).
+// Radices 2, 3, 4 and 5 use the usual symmetric forms; 7 the direct sum with
+// the roots wr[] (exp(-2 pi i q / 7)).
+template <int R, bool INV>
+__device__ inline void sep_dft(float2 (&u)[R], const float2 *wr)
+{
+    auto add = [](float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); };
+    auto sub = [](float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); };
+    auto scl = [](float2 a, float s) { return make_float2(a.x * s, a.y * s); };
+    if constexpr (R == 2) {
+        const float2 a = u[0], b = u[1];
+        u[0] = add(a, b);
+        u[1] = sub(a, b);
+    } else if constexpr (R == 4) {
+        const float2 s02 = add(u[0], u[2]), d02 = sub(u[0], u[2]);
+        const float2 s13 = add(u[1], u[3]), d13 = mul_mi<INV>(sub(u[1], u[3]));
+        u[0] = add(s02, s13);
+        u[2] = sub(s02, s13);
+        u[1] = add(d02, d13);
+        u[3] = sub(d02, d13);
+    } else if constexpr (R == 3) {
+        constexpr float h = 0.866025403784438646763723f;     // sin(2 pi / 3)
+        const float2 t1 = add(u[1], u[2]);
+        const float2 t2 = sub(u[0], scl(t1, 0.5f));
+        const float2 t3 = mul_mi<INV>(scl(sub(u[1], u[2]), h));
+        u[0] = add(u[0], t1);
+        u[1] = add(t2, t3);
+        u[2] = sub(t2, t3);
+    } else if constexpr (R == 5) {
+        constexpr float c1 = 0.309016994374947424102293f;     // cos(2 pi / 5)
+        constexpr float c2 = -0.809016994374947424102293f;    // cos(4 pi / 5)
+        constexpr float s1 = 0.951056516295153572116439f;     // sin(2 pi / 5)
+        constexpr float s2 = 0.587785252292473129168706f;     // sin(4 pi / 5)
+        const float2 t1 = add(u[1], u[4]), t2 = add(u[2], u[3]);
+        const float2 t3 = sub(u[1], u[4]), t4 = sub(u[2], u[3]);
+        const float2 a1 = add(u[0], add(scl(t1, c1), scl(t2, c2)));
+        const float2 a2 = add(u[0], add(scl(t1, c2), scl(t2, c1)));
+        const float2 b1 = mul_mi<INV>(add(scl(t3, s1), scl(t4, s2)));
+        const float2 b2 = mul_mi<INV>(sub(scl(t3, s2), scl(t4, s1)));
+        u[0] = add(u[0], add(t1, t2));
+        u[1] = add(a1, b1);
+        u[4] = sub(a1, b1);
+        u[2] = add(a2, b2);
+        u[3] = sub(a2, b2);
+    } else {
+        float2 o[R];
+#pragma unroll
+        for (int qo = 0; qo < R; ++qo) {
+            float2 acc = u[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                const float2 w = wr[(q * qo) % R];
+                const float2 t = INV ? cmulf_conj(u[q], w) : cmulf(u[q], w);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            o[qo] = acc;
+        }
+#pragma unroll
+        for (int qo = 0; qo < R; ++qo) u[qo] = o[qo];
+    }
+}
+
 // One Stockham pass of radix R over every pixel: x -> y.  p = product of the
 // radices of the earlier passes; tw[k R + q] = exp(-2 pi i q k / (p R)) for
 // k < p; wr[q] = exp(-2 pi i q / R).  INV uses the conjugates.
@@ -60,18 +127,9 @@ __device__ void sep_pass(const float2 *__restrict__ x, float2 *__restrict__ y, i
             u[q] = v;
         }
         const int j = (i - k) * R + k;
+        sep_dft<R, INV>(u, wr);
 #pragma unroll
-        for (int qo = 0; qo < R; ++qo) {
-            float2 s = u[0];
-#pragma unroll
-            for (int q = 1; q < R; ++q) {
-                const float2 w = wr[(q * qo) % R];
-                const float2 t = INV ? cmulf_conj(u[q], w) : cmulf(u[q], w);
-                s.x += t.x;
-                s.y += t.y;
-            }
-            y[(j + qo * p) * kSepPix + px] = s;
-        }
+        for (int qo = 0; qo < R; ++qo) y[(j + qo * p) * kSepPix + px] = u[qo];
     }
 }
 

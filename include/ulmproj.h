@@ -238,8 +238,9 @@ int32_t ulm_pair_workspace_size(const ulm_ctx_t *ctx, int32_t capacity, size_t *
  * i's slab and i's x in j's slab.  A pair is kept when each is the other's
  * candidate closest to a unit ratio, max(I_i/I_j, I_j/I_i) (ties to the smaller
  * index); its 3D position is (x_i, y_j, (z_i + z_j) / 2).
- *   locs   [capacity] ulm_loc_t, device, sorted by (plane, frame) as the
- *          localisers write them; the first min(*count, capacity) are used.
+ *   locs   [capacity] ulm_loc_t, device, 16-byte aligned, sorted by (plane,
+ *          frame) as the localisers write them; the first min(*count, capacity)
+ *          are used.
  *   out    [out_capacity] ulm_loc3d_t, device: pairs sorted by (frame, idx_xz);
  *   out_count int32, device: total pairs (may exceed out_capacity; then
  *          ulm_check_status(ctx, ws, out_count, out_capacity) returns OVERFLOW).

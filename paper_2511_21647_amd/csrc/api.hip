@@ -646,6 +646,7 @@ extern "C" int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const 
     if (!pws || pws_bytes < pair_workspace_bytes(ctx->geo.n_planes, ctx->geo.n_frames, std::max(capacity, 1)))
         return fail(ULM_ERR_INVALID_ARG, "pairing workspace missing or too small");
     if (((uintptr_t)pws & 255) != 0) return fail(ULM_ERR_INVALID_ARG, "pairing workspace not 256-byte aligned");
+    if (((uintptr_t)locs & 15) != 0) return fail(ULM_ERR_INVALID_ARG, "localisation list not 16-byte aligned");
     HIP_TRY(launch_pairing(ctx, locs, count, capacity, out, out_capacity, out_count, (char *)pws,
                            (hipStream_t)stream),
             "ulm_pair_planes");

@@ -57,17 +57,19 @@ __global__ void pair_bounds_kernel(const ulm_loc_t *__restrict__ locs, const int
     bounds[2 * key + 1] = lower(key + 1);
 }
 
-// cost of pairing XZ record a with YZ record b, or +inf if not a candidate
-__device__ inline float pair_cost(const ulm_loc_t &a, const ulm_loc_t &b, int B, int per) {
-    if (!(fabsf(a.z - b.z) <= 1.0f)) return INFINITY;
-    if (!(a.intensity > 0.f && b.intensity > 0.f)) return INFINITY;
-    const float rho = a.intensity / b.intensity;
+// cost of pairing an XZ record with a YZ record, each given as (z, u, ncc,
+// intensity), or +inf if they are not candidates (the slab test is separate)
+__device__ inline float pair_cost(float4 xz, float4 yz) {
+    if (!(fabsf(xz.x - yz.x) <= 1.0f)) return INFINITY;
+    if (!(xz.w > 0.f && yz.w > 0.f)) return INFINITY;
+    const float rho = xz.w / yz.w;
     if (!(rho >= 0.9f && rho <= 1.11f)) return INFINITY;
-    if (B > 1) {
-        const int ba = a.plane, bb = b.plane - B;                  // slabs of the two records
-        if (slab_of(b.u, per) != ba || slab_of(a.u, per) != bb) return INFINITY;
-    }
-    return fmaxf(rho, b.intensity / a.intensity);
+    return fmaxf(rho, yz.w / xz.w);
+}
+
+// (z, u, ncc, intensity) of record r: the second 16 bytes of the record
+__device__ inline float4 loc_zuni(const ulm_loc_t *locs, int r) {
+    return *reinterpret_cast<const float4 *>(&locs[r].z);
 }
 
 __global__ __launch_bounds__(256) void pair_best_kernel(PairArgs a)
@@ -75,14 +77,16 @@ __global__ __launch_bounds__(256) void pair_best_kernel(PairArgs a)
     const int f = blockIdx.x, p = blockIdx.y;
     const int lo = a.bounds[2 * (p * a.F + f)], hi = a.bounds[2 * (p * a.F + f) + 1];
     const bool xz = p < a.B;
+    // with slabs, a candidate's u must lie in this plane's slab; the record's own
+    // u picks the one segment of the other orientation that can hold its partner
+    const int want = xz ? p : p - a.B;
     for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-        const ulm_loc_t me = a.locs[r];
-        // the other orientation's segment that can hold my partner
+        const float4 me = loc_zuni(a.locs, r);
         int q;
         if (a.B == 1) {
             q = xz ? 1 : 0;
         } else {
-            const int sl = slab_of(me.u, a.per);
+            const int sl = slab_of(me.y, a.per);
             if (sl < 0 || sl >= a.B) {       // outside every slab: no partner
                 a.best[r] = -1;
                 continue;
@@ -92,9 +96,11 @@ __global__ __launch_bounds__(256) void pair_best_kernel(PairArgs a)
         const int clo = a.bounds[2 * (q * a.F + f)], chi = a.bounds[2 * (q * a.F + f) + 1];
         float bc = INFINITY;
         int bi = -1;
+#pragma unroll 4
         for (int c = clo; c < chi; ++c) {
-            const ulm_loc_t o = a.locs[c];
-            const float cost = xz ? pair_cost(me, o, a.B, a.per) : pair_cost(o, me, a.B, a.per);
+            const float4 o = loc_zuni(a.locs, c);
+            float cost = xz ? pair_cost(me, o) : pair_cost(o, me);
+            if (a.B > 1 && slab_of(o.y, a.per) != want) cost = INFINITY;
             if (cost < bc) {            // strict: the first (smallest index) minimum wins
                 bc = cost;
                 bi = c;

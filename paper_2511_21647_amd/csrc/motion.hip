@@ -139,19 +139,24 @@ __global__ __launch_bounds__(256) void mot_corr_kernel(const float2 *__restrict_
     const int npx = rows * a.nu;
     const int f0 = fb * kMotFrames;
     const float2 *Sb = S + (size_t)s * a.F * a.npix + (size_t)z0 * a.nu;
-    for (int p0 = 0; p0 < npx; p0 += kMotStage) {
-        __syncthreads();                                // Bs written / previous As consumed
-        const int p = p0 + t;
+    // the next step's 32 frames of this thread's pixel, in flight during the MFMAs
+    float2 xa[kMotFrames];
+    auto fetch = [&](int p0n) {
+        const int p = p0n + t;
+#pragma unroll
         for (int fl = 0; fl < kMotFrames; ++fl) {
             const int f = f0 + fl;
-            float v = 0.f;
-            if (f < a.F && p < npx) {
-                const float2 x = Sb[(size_t)f * a.npix + p];
-                v = sqrtf(x.x * x.x + x.y * x.y);
-            }
-            As[fl * kMotAS + t] = v;
+            xa[fl] = (f < a.F && p < npx) ? Sb[(size_t)f * a.npix + p] : make_float2(0.f, 0.f);
         }
+    };
+    fetch(0);
+    for (int p0 = 0; p0 < npx; p0 += kMotStage) {
+        __syncthreads();                                // Bs written / previous As consumed
+#pragma unroll
+        for (int fl = 0; fl < kMotFrames; ++fl)
+            As[fl * kMotAS + t] = sqrtf(xa[fl].x * xa[fl].x + xa[fl].y * xa[fl].y);
         __syncthreads();
+        if (p0 + kMotStage < npx) fetch(p0 + kMotStage);
         {   // sums of a and a^2 per frame: 8 threads per frame, 32 pixels each
             const int fl = t >> 3, q = t & 7;
             float s1 = 0.f, s2 = 0.f;
@@ -167,18 +172,23 @@ __global__ __launch_bounds__(256) void mot_corr_kernel(const float2 *__restrict_
             d1 += s1;
             d2 += s2;
         }
-        // pixels p0 + 128 ph .. p0 + 128 ph + 127, two per MFMA
+        // pixels p0 + 128 ph .. p0 + 128 ph + 127, two per MFMA; (pz, pu) of this
+        // lane's pixel advance by two per step (pixels past the band read an
+        // in-band reference value and contribute a = 0)
+        int pz = (p0 + ph * 128 + hk) / a.nu, pu = (p0 + ph * 128 + hk) - pz * a.nu;
 #pragma unroll 2
         for (int st = 0; st < 64; ++st) {
             const int pl = ph * 128 + 2 * st + hk;
             const float av = As[i32 * kMotAS + pl];
-            const int pp = min(p0 + pl, npx - 1);
-            const int pz = pp / a.nu, pu = pp - pz * a.nu;
-            const int base = (pz + L) * W2 + pu + L;
+            const int base = (min(pz, rows - 1) + L) * W2 + pu + L;
 #pragma unroll
             for (int tt = 0; tt < NH; ++tt)
                 if (tt < nt_here)
                     acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Bs[base - off[tt]], acc[tt], 0, 0, 0);
+            pu += 2;
+            const bool wrap = pu >= a.nu;
+            pu -= wrap ? a.nu : 0;
+            pz += wrap ? 1 : 0;
         }
     }
     // sum the two waves of each tile half in a fixed order, in LDS

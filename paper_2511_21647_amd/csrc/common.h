@@ -68,7 +68,7 @@ struct Workspace {
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
     size_t vbuf, pbuf;  // [planes][2][F] c128      column / p exchange (by step parity)
-    size_t bar;         // [planes] i32             grid-barrier counters
+    size_t bar;         // [planes][32] i32         grid-barrier flags (one per work-group)
     size_t eflag;       // [planes] i32
     size_t fmax;        // [planes][F] f32
     size_t band_cnt;    // [planes][F][bands] i32

@@ -6,6 +6,8 @@
 
 namespace ulm {
 
+constexpr int kCoopMaxW = 32;      // work-groups per plane (barrier flags per plane)
+
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)
     double2 *H;         // [planes][F][F] row k: Householder vector v_k (entries k+1..F-1)
@@ -18,7 +20,7 @@ struct EigArgs {
     double2 *xscr;      // [planes][c][F]
     double2 *vbuf;      // [planes][2][F] published columns (double-buffered by step parity)
     double2 *pbuf;      // [planes][2][F] published p = tau A v
-    int *bar;           // [planes] barrier counters, zero at launch
+    int *bar;           // [planes][kCoopMaxW] barrier flags, zero at launch
     int *flag;          // [planes] non-finite input
     int *status;
     int F, c, W;

@@ -94,15 +94,17 @@ __device__ inline double2 ld_c2(const double2 *p) {
     return make_double2(ld_c((const double *)p), ld_c((const double *)p + 1));
 }
 
-// Grid barrier among the W work-groups of one plane.  Returns false if the
-// wait timed out (the caller then exits).
-__device__ inline bool plane_barrier(int *cnt, int target, int *abort_s, int *status) {
+// Grid barrier among the W work-groups of one plane: work-group w publishes
+// the number of barriers it has reached in its own flag, and lanes 0..W-1 of
+// the first wave each wait for one work-group's flag, so no single counter is
+// contended.  Returns false if the wait timed out (the caller then exits).
+__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)threadIdx.x < W) {
         int spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1 << 23)) {
                 *abort_s = 1;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     // double-buffered exchange areas (by step parity): p and the next column
     double2 *pbuf = a.pbuf + (size_t)plane * 2 * F;
     double2 *cbuf = a.vbuf + (size_t)plane * 2 * F;
-    int *cnt = a.bar + plane;
+    int *flags = a.bar + (size_t)plane * kCoopMaxW;
     int nbar = 0;
 
     // load own columns (A[i][j] = conj(C[j][i]), contiguous in i) and check them
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     // the owner of column 0 publishes it
     if (w == 0)
         for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + i, Acol[i]);
-    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
     if (__hip_atomic_load(a.flag + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         if (w == 0) {
             double2 *V = a.V + (size_t)plane * F * (c > 0 ? c : 1);
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             if (j == k + 1)    // publish the next column (rows > k) for every work-group
                 for (int i = k + 1 + lane; i < F; i += 64) st_c2(cbuf + par * F + i, col[i]);
         }
-        if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
         // every work-group reads all of p and the next column, and forms p^H v itself
         double ppr = 0.0, ppi = 0.0;
         for (int i = t; i < F; i += kCoopThreads) {
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         st_c(e + F - 1, 0.0);
         st_c2(tau + F - 1, make_double2(0.0, 0.0));
     }
-    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 2. every eigenvalue by multisection on Sturm counts: one wave per
     //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
         }
     }
-    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
     if (c <= 0) return;
 
     // 3. inverse iteration for eigenvector vi of T (the vi-th largest
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         }
         __syncthreads();
     }
-    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 4. work-group 0: two passes of classical Gram-Schmidt over the c vectors
     //    (staged in LDS), then normalise
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         for (int i = t; i < c * F; i += kCoopThreads)
             ts[(size_t)(i / F) * 6 * F + 4 * F + (i % F)] = Y[i];
     }
-    if (!plane_barrier(cnt, ++nbar * W, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
     //    x held in registers (lane owns rows lane + 64 m), the next reflector
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
 }
 
-int eigen_coop_width(int F) { return std::max(1, std::min(32, cdiv(F, 10))); }
+int eigen_coop_width(int F) { return std::max(1, std::min(kCoopMaxW, cdiv(F, 10))); }
 
 size_t eigen_coop_lds(int F, int c) {
     if (F > 64 * kCoopRows) return SIZE_MAX;

@@ -588,10 +588,8 @@ __global__ __launch_bounds__(kEigThreads) void eigen_kernel(
 
 __global__ void clear_status_kernel(int *status, int *bar, int *eflag, int planes) {
     if (threadIdx.x == 0) *status = 0;
-    for (int i = threadIdx.x; i < planes; i += blockDim.x) {
-        bar[i] = 0;
-        eflag[i] = 0;
-    }
+    for (int i = threadIdx.x; i < planes * kCoopMaxW; i += blockDim.x) bar[i] = 0;
+    for (int i = threadIdx.x; i < planes; i += blockDim.x) eflag[i] = 0;
 }
 
 // ---------------------------------------------------------------- removal

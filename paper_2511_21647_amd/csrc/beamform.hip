@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
     const int f = lw % g.n_frames, o = lw / g.n_frames;
     const int tu = ti % n_tu, tz = ti / n_tu;
     const int c = threadIdx.x % kFirTileU;
-    const int rg = threadIdx.x / kFirTileU;          // 4 groups of 8 rows
+    const int rg = threadIdx.x / kFirTileU;          // 8 groups of 8 rows
     const int u = tu * kFirTileU + c;
     const int l0 = tz * kFirTileZ;
     const size_t plane = (size_t)g.nz * g.nu;

@@ -13,8 +13,9 @@ constexpr int kDasTileU = 32;      // tile: 8 rows (z) x 32 columns (u)
 constexpr int kDasTileZ = 8;
 constexpr int kDasFrames = 16;     // frames beamformed per delay evaluation
 
-constexpr int kFirTileZ = 32;
-constexpr int kFirTileU = 64;
+constexpr int kFirTileZ = 64;      // stage-2 tile: 64 rows (8 per thread) x 32 columns
+constexpr int kFirTileU = 32;
+static_assert(8 * (256 / kFirTileU) == kFirTileZ, "stage-2 tile: 8 rows per thread");
 constexpr int kFirMaxTaps = 48;
 constexpr int kFirGroup = 4;       // slabs per stage-2 work-group (many-slab projections)
 

@@ -621,6 +621,7 @@ __global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
     double2 y[CM];
 #pragma unroll
     for (int i = 0; i < CM; ++i) y[i] = make_double2(0.0, 0.0);
+#pragma unroll 4
     for (int g = 0; g < F; ++g) {
         const float2 xf = col[(size_t)g * npix];
         const double xr = xf.x, xi = xf.y;
@@ -632,6 +633,7 @@ __global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
             y[i].y = fma(xr, v.y, fma(xi, v.x, y[i].y));
         }
     }
+#pragma unroll 4
     for (int f = 0; f < F; ++f) {
         const float2 xf = col[(size_t)f * npix];
         const double2 *vf = Vp + (size_t)f * CM;

@@ -384,17 +384,24 @@ __global__ __launch_bounds__(256) void cnn_head_decode_kernel(
         unsigned bits = 0;
         float vals[kR];
         if (x < W) {
+            // fine rows i-1..i+1 and fine columns -1..8 around this thread's 8 pixels,
+            // read once (fine offsets are taken within coarse rows y-1..y+1 and
+            // columns x-1..x+1 of the chunk)
+            float nv[3][kR + 2];
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int c = 0; c < kR + 2; ++c) {
+                    const int fi = 7 + i + dz, fj = 7 + c;
+                    nv[dz][c] = hs[fi >> 3][cx + (fj >> 3)][(fi & 7) * kR + (fj & 7)];
+                }
 #pragma unroll
             for (int j = 0; j < kR; ++j) {
-                const float v = hs[1][1 + cx][i * kR + j];
+                const float v = nv[1][j + 1];
                 vals[j] = v;
-                auto nb8 = [&](int dz, int du) {
-                    const int fi = 8 + i + dz, fj = 8 + j + du;      // fine offsets within rows y-1..y+1
-                    return hs[fi >> 3][cx + (fj >> 3)][(fi & 7) * kR + (fj & 7)];
-                };
-                const bool cand = v >= thr && v > nb8(-1, -1) && v > nb8(-1, 0) &&
-                                  v > nb8(-1, 1) && v > nb8(0, -1) && v >= nb8(0, 1) &&
-                                  v >= nb8(1, -1) && v >= nb8(1, 0) && v >= nb8(1, 1);
+                const bool cand = v >= thr && v > nv[0][j] && v > nv[0][j + 1] && v > nv[0][j + 2] &&
+                                  v > nv[1][j] && v >= nv[1][j + 2] && v >= nv[2][j] &&
+                                  v >= nv[2][j + 1] && v >= nv[2][j + 2];
                 bits |= cand ? 1u << j : 0u;
             }
         }

@@ -32,6 +32,7 @@ namespace ulm {
 constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
 constexpr int kCoopRows = 8;     // back-transformation rows per lane: F <= 512
+constexpr int kChains = 4;       // eigenvalues bisected together per wave: F <= 4 x 4 x 32
 
 
 __device__ inline double2 cmul2(double2 a, double2 b) {
@@ -115,17 +116,6 @@ __device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *ab
     }
     __syncthreads();
     return *abort_s == 0;
-}
-
-__device__ inline int sturm(const double *d, const double *e2, int n, double x, double pivmin) {
-    double q = d[0] - x;
-    int cnt = q < 0.0;
-    for (int i = 1; i < n; ++i) {
-        if (fabs(q) <= pivmin) q = -pivmin;
-        q = d[i] - x - e2[i - 1] / q;
-        cnt += q < 0.0;
-    }
-    return cnt;
 }
 
 // Reflector of the unblocked Hermitian reduction (LAPACK's elementary
@@ -330,26 +320,73 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     lo_b -= 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
     hi_b += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
     double *lam = a.lam + (size_t)plane * F;
-    for (int idx = w * kCoopWaves + wave; idx < F; idx += W * kCoopWaves) {
-        const int target = F - 1 - idx;          // the eigenvalue with `target` below it
-        double lo = lo_b, hi = hi_b;
+    {
+        // wave gw bisects eigenvalues gw, gw + stride, ... (at most kChains) at
+        // once: their Sturm recurrences are interleaved in one loop, so the
+        // divisions of independent chains overlap
+        const int gw = w * kCoopWaves + wave, stride = W * kCoopWaves;
+        double lo[kChains], hi[kChains], x[kChains];
+        bool act[kChains];
+#pragma unroll
+        for (int r = 0; r < kChains; ++r) {
+            act[r] = gw + r * stride < F;
+            lo[r] = lo_b;
+            hi[r] = hi_b;
+        }
         for (int it = 0; it < 64; ++it) {
-            if (hi - lo <= 2.0 * DBL_EPSILON * tnorm) break;
-            const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-            const bool above = sturm(sd, se2, F, x, pivmin) > target;
-            const unsigned long long m = __ballot(above);
-            // counts grow with x: the eigenvalue lies between the last lane below
-            // and the first lane above
-            const int first = m ? __ffsll((long long)m) - 1 : 64;
-            const double nlo = first > 0 ? __shfl(x, first - 1) : lo;
-            const double nhi = first < 64 ? __shfl(x, first) : hi;
-            if (nlo == lo && nhi == hi) break;
-            lo = nlo;
-            hi = nhi;
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < kChains; ++r) {
+                if (act[r] && hi[r] - lo[r] <= 2.0 * DBL_EPSILON * tnorm) act[r] = false;
+                x[r] = lo[r] + (hi[r] - lo[r]) * (double)(lane + 1) / 65.0;
+                any = any || act[r];
+            }
+            if (!any) break;
+            int cnt[kChains];
+            double q[kChains];
+#pragma unroll
+            for (int r = 0; r < kChains; ++r) {
+                q[r] = sd[0] - x[r];
+                cnt[r] = q[r] < 0.0;
+            }
+            for (int i = 1; i < F; ++i) {
+                const double di = sd[i], e2 = se2[i - 1];
+#pragma unroll
+                for (int r = 0; r < kChains; ++r) {
+                    if (fabs(q[r]) <= pivmin) q[r] = -pivmin;
+                    // e2 / q through the hardware reciprocal and one Newton step
+                    // (within an ulp or two: the count is a sign test, and the
+                    // bracket ends at 2 eps |T| anyway)
+                    const double r0 = __builtin_amdgcn_rcp(q[r]);
+                    const double rq = fma(r0, fma(-q[r], r0, 1.0), r0);
+                    q[r] = (di - x[r]) - e2 * rq;
+                    cnt[r] += q[r] < 0.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kChains; ++r) {
+                if (!act[r]) continue;
+                const int target = F - 1 - (gw + r * stride);     // eigenvalues below this one
+                const unsigned long long m = __ballot(cnt[r] > target);
+                // counts grow with x: the eigenvalue lies between the last lane below
+                // and the first lane above
+                const int first = m ? __ffsll((long long)m) - 1 : 64;
+                const double nlo = first > 0 ? __shfl(x[r], first - 1) : lo[r];
+                const double nhi = first < 64 ? __shfl(x[r], first) : hi[r];
+                if (nlo == lo[r] && nhi == hi[r]) act[r] = false;
+                lo[r] = nlo;
+                hi[r] = nhi;
+            }
         }
         if (lane == 0) {
-            st_c(lam + idx, 0.5 * (lo + hi));
-            if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
+#pragma unroll
+            for (int r = 0; r < kChains; ++r) {
+                const int idx = gw + r * stride;
+                if (idx < F) {
+                    st_c(lam + idx, 0.5 * (lo[r] + hi[r]));
+                    if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo[r] + hi[r]);
+                }
+            }
         }
     }
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
@@ -540,7 +577,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
 int eigen_coop_width(int F) { return std::max(1, std::min(kCoopMaxW, cdiv(F, 10))); }
 
 size_t eigen_coop_lds(int F, int c) {
-    if (F > 64 * kCoopRows) return SIZE_MAX;
+    if (F > 64 * kCoopRows || F > kChains * kCoopWaves * eigen_coop_width(F)) return SIZE_MAX;
     const int W = eigen_coop_width(F);
     // reduction: own columns + 4 vectors; tail: d, e^2 and either the six LU
     // arrays or the c Gram-Schmidt vectors plus their dots

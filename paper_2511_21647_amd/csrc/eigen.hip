@@ -32,7 +32,8 @@ namespace ulm {
 constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
 constexpr int kCoopRows = 8;     // back-transformation rows per lane: F <= 512
-constexpr int kChains = 4;       // eigenvalues bisected together per wave: F <= 4 x 4 x 32
+constexpr int kPoints = 16;      // multisection points per eigenvalue and round
+constexpr int kGroups = 64 / kPoints;   // eigenvalues per wave: F <= kGroups x 4 waves x W
 
 
 __device__ inline double2 cmul2(double2 a, double2 b) {
@@ -321,72 +322,50 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     hi_b += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
     double *lam = a.lam + (size_t)plane * F;
     {
-        // wave gw bisects eigenvalues gw, gw + stride, ... (at most kChains) at
-        // once: their Sturm recurrences are interleaved in one loop, so the
-        // divisions of independent chains overlap
-        const int gw = w * kCoopWaves + wave, stride = W * kCoopWaves;
-        double lo[kChains], hi[kChains], x[kChains];
-        bool act[kChains];
-#pragma unroll
-        for (int r = 0; r < kChains; ++r) {
-            act[r] = gw + r * stride < F;
-            lo[r] = lo_b;
-            hi[r] = hi_b;
-        }
-        for (int it = 0; it < 64; ++it) {
-            bool any = false;
-#pragma unroll
-            for (int r = 0; r < kChains; ++r) {
-                if (act[r] && hi[r] - lo[r] <= 2.0 * DBL_EPSILON * tnorm) act[r] = false;
-                x[r] = lo[r] + (hi[r] - lo[r]) * (double)(lane + 1) / 65.0;
-                any = any || act[r];
-            }
-            if (!any) break;
-            int cnt[kChains];
-            double q[kChains];
-#pragma unroll
-            for (int r = 0; r < kChains; ++r) {
-                q[r] = sd[0] - x[r];
-                cnt[r] = q[r] < 0.0;
-            }
+        // wave gw bisects eigenvalues kGroups gw + g (g = lane / kPoints): the
+        // kPoints lanes of a group count at kPoints interior points of its
+        // bracket, so each round narrows it (kPoints + 1)-fold
+        const int gw = w * kCoopWaves + wave;
+        const int g = lane / kPoints, pi = lane % kPoints;
+        const int idx = gw * kGroups + g;
+        const bool mine = idx < F;
+        const int target = F - 1 - idx;                   // eigenvalues below this one
+        double lo = lo_b, hi = hi_b;
+        bool act = mine;
+        for (int it = 0; it < 200; ++it) {
+            if (act && hi - lo <= 2.0 * DBL_EPSILON * tnorm) act = false;
+            if (__ballot(act) == 0ull) break;
+            const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(kPoints + 1);
+            double q = sd[0] - x;
+            int cnt = q < 0.0;
+#pragma unroll 4
             for (int i = 1; i < F; ++i) {
-                const double di = sd[i], e2 = se2[i - 1];
-#pragma unroll
-                for (int r = 0; r < kChains; ++r) {
-                    if (fabs(q[r]) <= pivmin) q[r] = -pivmin;
-                    // e2 / q through the hardware reciprocal and one Newton step
-                    // (within an ulp or two: the count is a sign test, and the
-                    // bracket ends at 2 eps |T| anyway)
-                    const double r0 = __builtin_amdgcn_rcp(q[r]);
-                    const double rq = fma(r0, fma(-q[r], r0, 1.0), r0);
-                    q[r] = (di - x[r]) - e2 * rq;
-                    cnt[r] += q[r] < 0.0;
-                }
+                if (fabs(q) <= pivmin) q = -pivmin;
+                // e2 / q through the hardware reciprocal and one Newton step
+                // (within an ulp or two: the count is a sign test, and the
+                // bracket ends at 2 eps |T| anyway)
+                const double r0 = __builtin_amdgcn_rcp(q);
+                const double rq = fma(r0, fma(-q, r0, 1.0), r0);
+                q = (sd[i] - x) - se2[i - 1] * rq;
+                cnt += q < 0.0;
             }
-#pragma unroll
-            for (int r = 0; r < kChains; ++r) {
-                if (!act[r]) continue;
-                const int target = F - 1 - (gw + r * stride);     // eigenvalues below this one
-                const unsigned long long m = __ballot(cnt[r] > target);
-                // counts grow with x: the eigenvalue lies between the last lane below
-                // and the first lane above
-                const int first = m ? __ffsll((long long)m) - 1 : 64;
-                const double nlo = first > 0 ? __shfl(x[r], first - 1) : lo[r];
-                const double nhi = first < 64 ? __shfl(x[r], first) : hi[r];
-                if (nlo == lo[r] && nhi == hi[r]) act[r] = false;
-                lo[r] = nlo;
-                hi[r] = nhi;
+            // counts grow with x: the eigenvalue lies between the last point
+            // below and the first point above
+            const unsigned long long m = __ballot(cnt > target);
+            const unsigned bits = (unsigned)((m >> (g * kPoints)) & ((1ull << kPoints) - 1ull));
+            const int first = bits ? __ffs(bits) - 1 : kPoints;
+            const double nlo = __shfl(x, g * kPoints + (first > 0 ? first - 1 : 0));
+            const double nhi = __shfl(x, g * kPoints + (first < kPoints ? first : kPoints - 1));
+            const double lo2 = first > 0 ? nlo : lo, hi2 = first < kPoints ? nhi : hi;
+            if (act && lo2 == lo && hi2 == hi) act = false;
+            if (act) {
+                lo = lo2;
+                hi = hi2;
             }
         }
-        if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < kChains; ++r) {
-                const int idx = gw + r * stride;
-                if (idx < F) {
-                    st_c(lam + idx, 0.5 * (lo[r] + hi[r]));
-                    if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo[r] + hi[r]);
-                }
-            }
+        if (mine && pi == 0) {
+            st_c(lam + idx, 0.5 * (lo + hi));
+            if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
         }
     }
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
@@ -409,6 +388,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             const double tiny = DBL_EPSILON * tnorm + pivmin;
             // factor: rows i, i+1 enter step i as (c0, c1 | sub) over (next0, next1)
             double c0 = sd[0] - lm, c1 = F > 1 ? se[0] : 0.0;
+#pragma unroll 4
             for (int i = 0; i + 1 < F; ++i) {
                 const double sub = se[i];
                 double n0 = sd[i + 1] - lm;
@@ -448,6 +428,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             for (int it = 0; it < 3; ++it) {
                 // forward: apply the row swaps and multipliers
                 double cur = y[0];
+#pragma unroll 4
                 for (int i = 0; i + 1 < F; ++i) {
                     const double nxt = y[i + 1];
                     const bool swp = sw[i] != 0.0;
@@ -461,6 +442,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 double x1 = y[F - 1] * iu[F - 1], x2 = 0.0;
                 y[F - 1] = x1;
                 double n2 = x1 * x1;
+#pragma unroll 4
                 for (int i = F - 2; i >= 0; --i) {
                     const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * iu[i];
                     y[i] = xi;
@@ -577,7 +559,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
 int eigen_coop_width(int F) { return std::max(1, std::min(kCoopMaxW, cdiv(F, 10))); }
 
 size_t eigen_coop_lds(int F, int c) {
-    if (F > 64 * kCoopRows || F > kChains * kCoopWaves * eigen_coop_width(F)) return SIZE_MAX;
+    if (F > 64 * kCoopRows || F > kGroups * kCoopWaves * eigen_coop_width(F)) return SIZE_MAX;
     const int W = eigen_coop_width(F);
     // reduction: own columns + 4 vectors; tail: d, e^2 and either the six LU
     // arrays or the c Gram-Schmidt vectors plus their dots

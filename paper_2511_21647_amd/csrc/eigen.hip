@@ -500,8 +500,8 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
-    //    x held in registers (lane owns rows lane + 64 m), the next reflector
-    //    prefetched while the current one is applied
+    //    x held in registers (lane owns rows lane + 64 m), the next two
+    //    reflectors prefetched while the current one is applied
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double2 *V = a.V + (size_t)plane * F * c;
     for (int vi = w * kCoopWaves + wave; vi < c; vi += W * kCoopWaves) {
@@ -519,13 +519,18 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 v[m] = (q > k && q < F) ? H[(size_t)k * F + q] : make_double2(0.0, 0.0);
             }
         };
+        // reflectors k-1 and k-2 are in flight while k is applied (an L2 round
+        // trip is several steps of this loop)
+        double2 vn2[kCoopRows];
         double2 tc = F >= 2 ? tau[F - 2] : make_double2(0.0, 0.0);
+        double2 tn1 = F >= 3 ? tau[F - 3] : make_double2(0.0, 0.0);
         if (F >= 2) fetch(F - 2, vc);
+        if (F >= 3) fetch(F - 3, vn);
         for (int k = F - 2; k >= 0; --k) {
-            double2 tn = make_double2(0.0, 0.0);
-            if (k > 0) {
-                tn = tau[k - 1];
-                fetch(k - 1, vn);
+            double2 tn2 = make_double2(0.0, 0.0);
+            if (k > 1) {
+                tn2 = tau[k - 2];
+                fetch(k - 2, vn2);
             }
             if (tc.x != 0.0 || tc.y != 0.0) {
                 double sr = 0.0, si = 0.0;
@@ -544,9 +549,13 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                     x[m] = make_double2(x[m].x - p.x, x[m].y - p.y);
                 }
             }
-            tc = tn;
+            tc = tn1;
+            tn1 = tn2;
 #pragma unroll
-            for (int m = 0; m < kCoopRows; ++m) vc[m] = vn[m];
+            for (int m = 0; m < kCoopRows; ++m) {
+                vc[m] = vn[m];
+                vn[m] = vn2[m];
+            }
         }
 #pragma unroll
         for (int m = 0; m < kCoopRows; ++m) {

@@ -137,7 +137,7 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.hvec = take(sizeof(double2) * planes * F * F);
     w.vbuf = take(sizeof(double2) * planes * 2 * F);
     w.pbuf = take(sizeof(double2) * planes * 2 * F);
-    w.bar = take(sizeof(int) * planes * 32);
+    w.bar = take(sizeof(int) * planes * kBarStride);
     w.eflag = take(sizeof(int) * planes);
     w.fmax = take(sizeof(float) * planes * F);
     w.band_cnt = take(sizeof(int) * planes * F * w.bands);

@@ -78,10 +78,14 @@ __device__ inline double bmax(double v, double *red) {
     return s;
 }
 
-// Cross-work-group traffic uses relaxed agent-scope atomics: plain loads and
-// stores with the system-coherence bit, so no L2 write-back or invalidation is
-// needed inside the reduction.  A work-group arrives at a barrier only after its
-// own stores have completed (s_waitcnt 0).
+// Cross-work-group loads are relaxed agent-scope atomics: loads with the
+// device-coherence bit, which miss the CU's L1 and read the L2.  A work-group
+// arrives at a barrier only after its own stores have completed (s_waitcnt 0).
+// Stores come in two kinds.  When every work-group of a plane runs on one XCD
+// (checked at launch from the hardware XCC id), they all share that XCD's L2,
+// and plain stores, complete once they reach it, are enough: this is the
+// "local" mode, and it shortens every barrier.  Otherwise stores are
+// agent-scope atomics too, which write through to memory.
 __device__ inline void st_c(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -95,15 +99,29 @@ __device__ inline void st_c2(double2 *p, double2 v) {
 __device__ inline double2 ld_c2(const double2 *p) {
     return make_double2(ld_c((const double *)p), ld_c((const double *)p + 1));
 }
+__device__ inline void put(double *p, double v, bool local) {
+    if (local) *p = v;
+    else st_c(p, v);
+}
+__device__ inline void put2(double2 *p, double2 v, bool local) {
+    if (local) *p = v;
+    else st_c2(p, v);
+}
+// The XCC (XCD) this wave runs on.
+__device__ inline int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xf); }
 
 // Grid barrier among the W work-groups of one plane: work-group w publishes
 // the number of barriers it has reached in its own flag, and lanes 0..W-1 of
 // the first wave each wait for one work-group's flag, so no single counter is
 // contended.  Returns false if the wait timed out (the caller then exits).
-__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status) {
+__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status,
+                                     bool local = false) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        if (local) flags[w] = step;
+        else __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if ((int)threadIdx.x < W) {
         int spins = 0;
         while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
@@ -177,7 +195,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     // double-buffered exchange areas (by step parity): p and the next column
     double2 *pbuf = a.pbuf + (size_t)plane * 2 * F;
     double2 *cbuf = a.vbuf + (size_t)plane * 2 * F;
-    int *flags = a.bar + (size_t)plane * kCoopMaxW;
+    int *flags = a.bar + (size_t)plane * kBarStride;
     int nbar = 0;
 
     // load own columns (A[i][j] = conj(C[j][i]), contiguous in i) and check them
@@ -197,6 +215,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     bad = bmax(bad, red);
     if (t == 0 && bad > 0.0) atomicOr(a.flag + plane, 1);
+    // work-group slot g is meant to run on XCD g mod 8, like every slot of its
+    // plane; one that does not switches the plane to agent-scope stores
+    if (t == 0 && xcc_id() != xcd) atomicOr(flags + kCoopMaxW, 1);
     // the owner of column 0 publishes it
     if (w == 0)
         for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + i, Acol[i]);
@@ -213,6 +234,8 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         }
         return;
     }
+    const bool local =
+        !a.agent_scope && __hip_atomic_load(flags + kCoopMaxW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     for (int i = t; i < F; i += kCoopThreads) scol[i] = ld_c2(cbuf + i);
     __syncthreads();
 
@@ -230,11 +253,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         reflector(scol, k, F, red, svn, tk, beta);
         __syncthreads();
         if (w == k % W) {
-            for (int i = k + 1 + t; i < F; i += kCoopThreads) st_c2(H + (size_t)k * F + i, svn[i]);
+            for (int i = k + 1 + t; i < F; i += kCoopThreads) put2(H + (size_t)k * F + i, svn[i], local);
             if (t == 0) {
-                st_c(d + k, scol[k].x);
-                st_c(e + k, beta);
-                st_c2(tau + k, tk);
+                put(d + k, scol[k].x, local);
+                put(e + k, beta, local);
+                put2(tau + k, tk, local);
             }
         }
         // own columns j > k: pending update, then p_j = tau_k sum_i conj(A[i][j]) v_i
@@ -257,11 +280,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             ar = wsum(ar);
             ai = wsum(ai);
             const double2 pj = cmul2(tk, make_double2(ar, ai));
-            if (lane == 0) st_c2(pbuf + par * F + j, pj);
+            if (lane == 0) put2(pbuf + par * F + j, pj, local);
             if (j == k + 1)    // publish the next column (rows > k) for every work-group
-                for (int i = k + 1 + lane; i < F; i += 64) st_c2(cbuf + par * F + i, col[i]);
+                for (int i = k + 1 + lane; i < F; i += 64) put2(cbuf + par * F + i, col[i], local);
         }
-        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
         // every work-group reads all of p and the next column, and forms p^H v itself
         double ppr = 0.0, ppi = 0.0;
         for (int i = t; i < F; i += kCoopThreads) {
@@ -289,11 +312,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             const double2 vi = sv[F - 1], pi = sp[F - 1];
             dl -= 2.0 * (vi.x * pi.x + vi.y * pi.y) + a2r * (vi.x * vi.x + vi.y * vi.y);
         }
-        st_c(d + F - 1, dl);
-        st_c(e + F - 1, 0.0);
-        st_c2(tau + F - 1, make_double2(0.0, 0.0));
+        put(d + F - 1, dl, local);
+        put(e + F - 1, 0.0, local);
+        put2(tau + F - 1, make_double2(0.0, 0.0), local);
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
 
     // 2. every eigenvalue by multisection on Sturm counts: one wave per
     //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
@@ -364,11 +387,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             }
         }
         if (mine && pi == 0) {
-            st_c(lam + idx, 0.5 * (lo + hi));
+            put(lam + idx, 0.5 * (lo + hi), local);
             if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
         }
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
     if (c <= 0) return;
 
     // 3. inverse iteration for eigenvector vi of T (the vi-th largest
@@ -454,11 +477,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 for (int i = 0; i < F; ++i) y[i] *= inv;
             }
             double *yo = ts + (size_t)vi * 6 * F + 4 * F;
-            for (int i = 0; i < F; ++i) yo[i] = y[i];
+            for (int i = 0; i < F; ++i) put(yo + i, y[i], local);
         }
         __syncthreads();
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
 
     // 4. work-group 0: two passes of classical Gram-Schmidt over the c vectors
     //    (staged in LDS), then normalise
@@ -495,9 +518,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             __syncthreads();
         }
         for (int i = t; i < c * F; i += kCoopThreads)
-            ts[(size_t)(i / F) * 6 * F + 4 * F + (i % F)] = Y[i];
+            put(ts + (size_t)(i / F) * 6 * F + 4 * F + (i % F), Y[i], local);
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
 
     // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
     //    x held in registers (lane owns rows lane + 64 m), the next two

@@ -12,6 +12,7 @@
 #include "eigen.h"
 
 #include <float.h>
+#include <stdlib.h>
 
 namespace ulm {
 
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(kEigThreads) void eigen_kernel(
 
 __global__ void clear_status_kernel(int *status, int *bar, int *eflag, int planes) {
     if (threadIdx.x == 0) *status = 0;
-    for (int i = threadIdx.x; i < planes * kCoopMaxW; i += blockDim.x) bar[i] = 0;
+    for (int i = threadIdx.x; i < planes * kBarStride; i += blockDim.x) bar[i] = 0;
     for (int i = threadIdx.x; i < planes; i += blockDim.x) eflag[i] = 0;
 }
 
@@ -697,6 +698,9 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         a.F = F;
         a.c = c;
         a.W = eigen_coop_width(F);
+        // diagnostic switch: agent-scope stores even where a plane's work-groups
+        // share one XCD (the results are the same bit for bit)
+        a.agent_scope = getenv("ULMPROJ_EIGEN_AGENT_SCOPE") != nullptr;
         a.planes = planes;
         a.plane0 = 0;
         if ((e = launch_eigen_coop(a, st)) != hipSuccess) return e;

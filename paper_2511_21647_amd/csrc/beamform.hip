@@ -42,9 +42,10 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
 #pragma unroll
         for (int r = 0; r < 8; ++r) acc[gb][r] = make_float2(0.f, 0.f);
 
-    for (int k = 0; k < g.n_angles; ++k) {
-        // union of the group's tap offsets: [lo, hi)
-        int lo = INT32_MAX, hi = INT32_MIN;
+    // union of the group's tap offsets for transmit k: [lo, hi)
+    auto span_of = [&](int k, int &lo, int &hi) {
+        lo = INT32_MAX;
+        hi = INT32_MIN;
 #pragma unroll
         for (int gb = 0; gb < G; ++gb)
             if (b0 + gb < g.n_blocks) {
@@ -52,16 +53,30 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
                 lo = min(lo, m.x);
                 hi = max(hi, m.x + m.y);
             }
-        const int rows = kFirTileZ + (hi - lo);    // each window reads one row past its last tap
+    };
+    // the slice tile of transmit k (rows l0 + lo .. , one row past the last tap
+    // of each window): element e = t + 256 i of the tile goes through pre[i]
+    constexpr int kPer = ((kFirTileZ + kFirMaxTaps) * kFirTileU + 255) / 256;
+    float2 pre[kPer];
+    auto fetch = [&](int k, int lo, int rows) {
         const float2 *src = S + ((size_t)(o * g.n_angles + k) * g.n_frames + f) * plane;
-        for (int e = threadIdx.x; e < rows * kFirTileU; e += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
             const int rr = e / kFirTileU, cc = e % kFirTileU;
             const int zz = l0 + lo + rr, uu = tu * kFirTileU + cc;
-            float2 v = make_float2(0.f, 0.f);
-            if (zz >= 0 && zz < g.nz && uu < g.nu) v = src[(size_t)zz * g.nu + uu];
-            tile[rr][cc] = v;
+            pre[i] = make_float2(0.f, 0.f);
+            if (rr < rows && zz >= 0 && zz < g.nz && uu < g.nu) pre[i] = src[(size_t)zz * g.nu + uu];
         }
-        __syncthreads();
+    };
+    auto stash = [&](int rows) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < rows * kFirTileU) tile[e / kFirTileU][e % kFirTileU] = pre[i];
+        }
+    };
+    auto filter = [&](int k, int lo_k) {
 #pragma unroll
         for (int gb = 0; gb < G; ++gb) {
             if (b0 + gb >= g.n_blocks) continue;
@@ -69,7 +84,7 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
             // 8 consecutive output rows per thread: a rotating window of 8 input rows
             // in registers, so each tap costs one LDS read instead of eight
             const float2 *h = taps + (size_t)(k * g.n_blocks + b0 + gb) * max_taps;
-            const int base = rg * 8 + (m.x - lo);
+            const int base = rg * 8 + (m.x - lo_k);
             float2 win[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) win[r] = tile[base + r][c];
@@ -92,7 +107,40 @@ __global__ __launch_bounds__(256) void stage2_fir_kernel(
             for (int uu = 0; uu < 8; ++uu)
                 if (tt + uu < m.y) step(tt + uu, uu);
         }
-        __syncthreads();
+    };
+    int lo, hi;
+    if constexpr (G == 1) {
+        // one slab: the next transmit's tile is loaded while this one is filtered
+        span_of(0, lo, hi);
+        fetch(0, lo, kFirTileZ + (hi - lo));
+        for (int k = 0; k < g.n_angles; ++k) {
+            stash(kFirTileZ + (hi - lo));
+            __syncthreads();
+            const int lo_k = lo;
+            if (k + 1 < g.n_angles) {
+                span_of(k + 1, lo, hi);
+                fetch(k + 1, lo, kFirTileZ + (hi - lo));
+            }
+            filter(k, lo_k);
+            __syncthreads();
+        }
+    } else {
+        // G slabs hold G x 8 accumulators: no registers to spare for a prefetch
+        for (int k = 0; k < g.n_angles; ++k) {
+            span_of(k, lo, hi);
+            const int rows = kFirTileZ + (hi - lo);
+            const float2 *src = S + ((size_t)(o * g.n_angles + k) * g.n_frames + f) * plane;
+            for (int e = threadIdx.x; e < rows * kFirTileU; e += blockDim.x) {
+                const int rr = e / kFirTileU, cc = e % kFirTileU;
+                const int zz = l0 + lo + rr, uu = tu * kFirTileU + cc;
+                float2 v = make_float2(0.f, 0.f);
+                if (zz >= 0 && zz < g.nz && uu < g.nu) v = src[(size_t)zz * g.nu + uu];
+                tile[rr][cc] = v;
+            }
+            __syncthreads();
+            filter(k, lo);
+            __syncthreads();
+        }
     }
     if (u >= g.nu) return;
 #pragma unroll

@@ -12,7 +12,7 @@ namespace ulm {
 // G slabs per work-group: for each transmit the slice tile covers the union of
 // the G slabs' tap ranges and is read from HBM once for all of them.
 template <int G>
-__global__ __launch_bounds__(256) void stage2_fir_kernel(
+__global__ __launch_bounds__(256, 4) void stage2_fir_kernel(
     const float2 *__restrict__ S, float2 *__restrict__ P, const float2 *__restrict__ taps,
     const int2 *__restrict__ meta, Geometry g, int max_taps)
 {

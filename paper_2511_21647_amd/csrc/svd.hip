@@ -66,16 +66,30 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
             acci[a][b] = f64x4{0, 0, 0, 0};
         }
 
-    for (int p0 = px0; p0 < px1; p0 += kGramStage) {
-        for (int e = threadIdx.x; e < 2 * kGramBlock * kGramStage; e += 256) {
+    // the next stage's pixels are loaded into registers while this stage's
+    // products run
+    constexpr int kPer = 2 * kGramBlock * kGramStage / 256;
+    float2 pre[kPer];
+    auto fetch = [&](int p0) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
             const int row = e / kGramStage, col = e % kGramStage;
             const int frame = row < kGramBlock ? I * kGramBlock + row : J * kGramBlock + row - kGramBlock;
             const int px = p0 + col;
-            float2 v = make_float2(0.f, 0.f);
-            if (frame < F && px < px1) v = src[(size_t)frame * npix + px];
-            lds[row][col] = v;
+            pre[i] = make_float2(0.f, 0.f);
+            if (frame < F && px < px1) pre[i] = src[(size_t)frame * npix + px];
+        }
+    };
+    fetch(px0);
+    for (int p0 = px0; p0 < px1; p0 += kGramStage) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            lds[e / kGramStage][e % kGramStage] = pre[i];
         }
         __syncthreads();
+        if (p0 + kGramStage < px1) fetch(p0 + kGramStage);
 #pragma unroll 4
         for (int step = 0; step < kGramStage / 2; ++step) {
             const int pxl = step * 2 + (kk >> 1);

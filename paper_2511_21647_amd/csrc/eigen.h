@@ -6,7 +6,8 @@
 
 namespace ulm {
 
-constexpr int kCoopMaxW = 32;      // work-groups per plane (barrier flags per plane)
+constexpr int kCoopMaxW = 32;      // work-groups per plane (one barrier flag each)
+constexpr int kPlaceWord = kBarStride - 1;  // per-plane word: a work-group off its XCD
 
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)

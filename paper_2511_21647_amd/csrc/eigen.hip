@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     if (t == 0 && bad > 0.0) atomicOr(a.flag + plane, 1);
     // work-group slot g is meant to run on XCD g mod 8, like every slot of its
     // plane; one that does not switches the plane to agent-scope stores
-    if (t == 0 && xcc_id() != xcd) atomicOr(flags + kCoopMaxW, 1);
+    if (t == 0 && xcc_id() != xcd) atomicOr(flags + kPlaceWord, 1);
     // the owner of column 0 publishes it
     if (w == 0)
         for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + i, Acol[i]);
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         return;
     }
     const bool local =
-        !a.agent_scope && __hip_atomic_load(flags + kCoopMaxW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        !a.agent_scope && __hip_atomic_load(flags + kPlaceWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     for (int i = t; i < F; i += kCoopThreads) scol[i] = ld_c2(cbuf + i);
     __syncthreads();
 

@@ -139,23 +139,23 @@ __device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *ab
 
 // Reflector of the unblocked Hermitian reduction (LAPACK's elementary
 // reflector convention): H^H x = (beta, 0, ...)^T, H = I - tau v v^H, v_0 = 1.
-// x = col[k+1 .. F); computed identically by every work-group.
+// x = col[k+1 .. F); computed identically by every work-group.  nrm_part is
+// this thread's share of |x_2..|^2 (its rows >= k+2); the sum's barriers also
+// publish col.
 __device__ inline void reflector(const double2 *col, int k, int F, double *red, double2 *v,
-                                 double2 &tk, double &beta) {
-    double nrm = 0.0;
-    for (int i = k + 2 + threadIdx.x; i < F; i += kCoopThreads)
-        nrm += col[i].x * col[i].x + col[i].y * col[i].y;
-    nrm = bsum(nrm, red);
+                                 double2 &tk, double &beta, double nrm_part) {
+    const double nrm = bsum(nrm_part, red);
     const double2 alpha = col[k + 1];
     tk = make_double2(0.0, 0.0);
     beta = alpha.x;
     double2 scale = make_double2(0.0, 0.0);
     if (nrm > 0.0 || alpha.y != 0.0) {
         beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + nrm), alpha.x);
-        tk = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double ib = 1.0 / beta;
+        tk = make_double2((beta - alpha.x) * ib, -alpha.y * ib);
         const double2 den = make_double2(alpha.x - beta, alpha.y);
-        const double dd = den.x * den.x + den.y * den.y;
-        scale = make_double2(den.x / dd, -den.y / dd);
+        const double idd = 1.0 / (den.x * den.x + den.y * den.y);
+        scale = make_double2(den.x * idd, -den.y * idd);
     }
     for (int i = k + 1 + threadIdx.x; i < F; i += kCoopThreads)
         v[i] = (i == k + 1) ? make_double2(1.0, 0.0) : cmul2(col[i], scale);
@@ -236,21 +236,22 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     const bool local =
         !a.agent_scope && __hip_atomic_load(flags + kPlaceWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    for (int i = t; i < F; i += kCoopThreads) scol[i] = ld_c2(cbuf + i);
-    __syncthreads();
+    // thread t owns rows t + 256 m of the column being reduced (scol) and of
+    // sv, sp; nrm_part is its share of the next reflector's |x|^2
+    double nrm_part = 0.0;
+    for (int i = t; i < F; i += kCoopThreads) {
+        const double2 x = ld_c2(cbuf + i);
+        scol[i] = x;
+        if (i >= 2) nrm_part += x.x * x.x + x.y * x.y;
+    }
 
     double a2r = 0.0;   // 2 Re(alpha) of the pending rank-2 update (step k-1)
     for (int k = 0; k + 1 < F; ++k) {
         const int par = k & 1;
-        // column k: pending update of step k-1 (rows >= k), then the reflector
-        if (k > 0) {
-            const double2 cpk = make_double2(sp[k].x, -sp[k].y), cvk = make_double2(sv[k].x, -sv[k].y);
-            for (int i = k + t; i < F; i += kCoopThreads) scol[i] = pending(scol[i], sv[i], sp[i], cpk, cvk, a2r);
-            __syncthreads();
-        }
+        // column k, with every update through step k-1 applied: its reflector
         double2 tk;
         double beta;
-        reflector(scol, k, F, red, svn, tk, beta);
+        reflector(scol, k, F, red, svn, tk, beta, nrm_part);
         __syncthreads();
         if (w == k % W) {
             for (int i = k + 1 + t; i < F; i += kCoopThreads) put2(H + (size_t)k * F + i, svn[i], local);
@@ -285,34 +286,54 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 for (int i = k + 1 + lane; i < F; i += 64) put2(cbuf + par * F + i, col[i], local);
         }
         if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
-        // every work-group reads all of p and the next column, and forms p^H v itself
+        // every work-group reads all of p and the next column, forms p^H v itself
+        // and applies the update of step k to column k+1 (rows > k)
+        constexpr int kOwn = 64 * kCoopRows / kCoopThreads;     // rows per thread: F <= 512
+        double2 pv[kOwn], cv[kOwn];
+        const double2 pk1 = ld_c2(pbuf + par * F + k + 1);
+#pragma unroll
+        for (int m = 0; m < kOwn; ++m) {
+            // all loads issued before any is used (rows <= k read a valid, unused slot)
+            const int i = t + kCoopThreads * m, ii = (i > k && i < F) ? i : F - 1;
+            pv[m] = ld_c2(pbuf + par * F + ii);
+            cv[m] = ld_c2(cbuf + par * F + ii);
+        }
         double ppr = 0.0, ppi = 0.0;
-        for (int i = t; i < F; i += kCoopThreads) {
-            // both loads issued before either is used (rows <= k read a valid, unused slot)
-            const int ii = i > k ? i : F - 1;
-            const double2 pv = ld_c2(pbuf + par * F + ii), cv = ld_c2(cbuf + par * F + ii);
-            if (i > k) {
-                const double2 dv = cjmul2(pv, svn[i]);
+#pragma unroll
+        for (int m = 0; m < kOwn; ++m) {
+            const int i = t + kCoopThreads * m;
+            if (i >= F) break;
+            const bool live = i > k;
+            const double2 vi = live ? svn[i] : make_double2(0.0, 0.0);
+            if (live) {
+                const double2 dv = cjmul2(pv[m], vi);
                 ppr += dv.x;
                 ppi += dv.y;
             }
-            sv[i] = i > k ? svn[i] : make_double2(0.0, 0.0);
-            sp[i] = i > k ? pv : make_double2(0.0, 0.0);
-            if (i > k) scol[i] = cv;
+            sv[i] = vi;
+            sp[i] = live ? pv[m] : make_double2(0.0, 0.0);
         }
-        const double2 pvh = bsum2(ppr, ppi, wpart);     // its syncs also publish sp, sv, scol
+        const double2 pvh = bsum2(ppr, ppi, wpart);     // its syncs also publish sp and sv
         // alpha = -1/2 tau (p^H v); the pending update uses 2 Re(alpha)
         const double2 al = cmul2(make_double2(-0.5 * tk.x, -0.5 * tk.y), pvh);
         a2r = 2.0 * al.x;
-    }
-    // last diagonal entry: pending update of step F-2 applied to A[F-1][F-1]
-    if (w == 0 && t == 0) {
-        double dl = scol[F - 1].x;
-        if (F >= 2) {
-            const double2 vi = sv[F - 1], pi = sp[F - 1];
-            dl -= 2.0 * (vi.x * pi.x + vi.y * pi.y) + a2r * (vi.x * vi.x + vi.y * vi.y);
+        const double2 cpk = make_double2(pk1.x, -pk1.y), cvk = make_double2(svn[k + 1].x, -svn[k + 1].y);
+        nrm_part = 0.0;
+#pragma unroll
+        for (int m = 0; m < kOwn; ++m) {
+            const int i = t + kCoopThreads * m;
+            if (i >= F) break;
+            if (i > k) {
+                const double2 x = pending(cv[m], sv[i], sp[i], cpk, cvk, a2r);
+                scol[i] = x;
+                if (i >= k + 3) nrm_part += x.x * x.x + x.y * x.y;
+            }
         }
-        put(d + F - 1, dl, local);
+    }
+    // last diagonal entry: column F-1 with the update of step F-2 applied
+    __syncthreads();
+    if (w == 0 && t == 0) {
+        put(d + F - 1, scol[F - 1].x, local);
         put(e + F - 1, 0.0, local);
         put2(tau + F - 1, make_double2(0.0, 0.0), local);
     }

@@ -37,6 +37,7 @@ size_t motion_lds_bytes(const Geometry &g, int L);
 hipError_t launch_motion(const ulm_ctx *ctx, const float2 *S, int ref, int L, float *disp,
                          float *motion, char *mws, hipStream_t st);
 bool separate_supported(int F);
+std::vector<float2> separate_twiddles(int F);
 hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, float2 *out,
                            hipStream_t st);
 size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
@@ -78,7 +79,7 @@ extern "C" const char *ulm_last_error(void) { return g_err.c_str(); }
 
 static void free_tables(ulm_ctx *ctx) {
     Tables &t = ctx->tab;
-    void *ptrs[] = {t.stx, t.sti, t.phz, t.rxd, t.rxp, t.win, t.taps, t.tap_meta, t.angles};
+    void *ptrs[] = {t.stx, t.sti, t.phz, t.rxd, t.rxp, t.win, t.taps, t.tap_meta, t.angles, t.sep_tw};
     for (void *p : ptrs) (void)hipFree(p);
 }
 
@@ -344,6 +345,14 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
         return cleanup(e, "hipMemcpy");
     if ((e = hipMemcpy(ctx->tab.angles, c.angles_rad, sizeof(double) * ULM_MAX_ANGLES, hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(e, "hipMemcpy");
+    {
+        const std::vector<float2> tw = separate_twiddles(c.n_frames);
+        if (!tw.empty()) {
+            if ((e = hipMalloc(&ctx->tab.sep_tw, sizeof(float2) * tw.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+            if ((e = hipMemcpy(ctx->tab.sep_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice)) != hipSuccess)
+                return cleanup(e, "hipMemcpy");
+        }
+    }
     int lds_max = 0;
     if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device)) != hipSuccess)
         return cleanup(e, "hipDeviceGetAttribute");

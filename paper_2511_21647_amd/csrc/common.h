@@ -52,6 +52,7 @@ struct Tables {
     double *angles;    // [K]       steering angles (simulator)
     int n_taps;        // maximum taps over (transmit, block)
     int fir_group;     // slabs per stage-2 work-group: 1 or kFirGroup
+    float2 *sep_tw;    // MB-separation FFT twiddles for F frames (null if F has a factor > 7)
 };
 
 // Words per plane of the eigensolver's barrier area: one grid-barrier flag per

@@ -16,6 +16,9 @@
 
 #include <math.h>
 
+#include <cmath>
+#include <vector>
+
 namespace ulm {
 
 constexpr int kSepPix = 16;                 // pixels per work-group
@@ -30,7 +33,9 @@ struct SepArgs {
     int n_pass;
     int radix[kSepMaxPass];
     int tw_off[kSepMaxPass];                // offset of each pass's twiddles in the table
+    unsigned pmag[kSepMaxPass];             // floor(2^32 / p) + 1 for the pass's p (0 when p = 1)
     int n_tw;                               // twiddle entries (all passes)
+    const float2 *twt;                      // [n_tw + 21] twiddles, then the radix roots
     int lo[kSepMaxSub], hi[kSepMaxSub];     // |k| range of each subset
 };
 
@@ -110,15 +115,16 @@ __device__ inline void sep_dft(float2 (&u)[R], const float2 *wr)
 
 // One Stockham pass of radix R over every pixel: x -> y.  p = product of the
 // radices of the earlier passes; tw[k R + q] = exp(-2 pi i q k / (p R)) for
-// k < p; wr[q] = exp(-2 pi i q / R).  INV uses the conjugates.
+// k < p; wr[q] = exp(-2 pi i q / R).  INV uses the conjugates.  i mod p comes
+// from a multiply-high by pmag = floor(2^32 / p) + 1, exact for i, p < 2^16.
 template <int R, bool INV>
 __device__ void sep_pass(const float2 *__restrict__ x, float2 *__restrict__ y, int F, int p,
-                         const float2 *tw, const float2 *wr)
+                         unsigned pmag, const float2 *tw, const float2 *wr)
 {
     const int nb = F / R;                                  // butterflies per pixel
     for (int e = threadIdx.x; e < nb * kSepPix; e += kSepThreads) {
         const int i = e / kSepPix, px = e % kSepPix;
-        const int k = i % p;
+        const int k = p == 1 ? 0 : i - (int)__umulhi((unsigned)i, pmag) * p;
         float2 u[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -143,11 +149,11 @@ __device__ float2 *sep_fft(float2 *a, float2 *b, const SepArgs &g, const float2 
         const int R = g.radix[s];
         const float2 *t = tw + g.tw_off[s];
         switch (R) {
-            case 2: sep_pass<2, INV>(a, b, g.F, p, t, wr + 0); break;
-            case 3: sep_pass<3, INV>(a, b, g.F, p, t, wr + 2); break;
-            case 4: sep_pass<4, INV>(a, b, g.F, p, t, wr + 5); break;
-            case 5: sep_pass<5, INV>(a, b, g.F, p, t, wr + 9); break;
-            default: sep_pass<7, INV>(a, b, g.F, p, t, wr + 14); break;
+            case 2: sep_pass<2, INV>(a, b, g.F, p, g.pmag[s], t, wr + 0); break;
+            case 3: sep_pass<3, INV>(a, b, g.F, p, g.pmag[s], t, wr + 2); break;
+            case 4: sep_pass<4, INV>(a, b, g.F, p, g.pmag[s], t, wr + 5); break;
+            case 5: sep_pass<5, INV>(a, b, g.F, p, g.pmag[s], t, wr + 9); break;
+            default: sep_pass<7, INV>(a, b, g.F, p, g.pmag[s], t, wr + 14); break;
         }
         __syncthreads();
         float2 *c = a;
@@ -170,29 +176,9 @@ __global__ __launch_bounds__(kSepThreads) void sep_kernel(const float2 *__restri
     const int plane = blockIdx.x / groups, px0 = (blockIdx.x % groups) * kSepPix;
     const int t = threadIdx.x;
 
-    // twiddles of every pass and the roots of unity of every radix (FP64 -> FP32)
-    {
-        int p = 1;
-        for (int s = 0; s < g.n_pass; ++s) {
-            const int R = g.radix[s];
-            for (int e = t; e < p * R; e += kSepThreads) {
-                const int k = e / R, q = e % R;
-                double sn, cs;
-                sincospi(-2.0 * q * k / (double)(p * R), &sn, &cs);
-                tw[g.tw_off[s] + e] = make_float2((float)cs, (float)sn);
-            }
-            p *= R;
-        }
-        const int base[5] = {0, 2, 5, 9, 14}, rad[5] = {2, 3, 4, 5, 7};
-        for (int e = t; e < 21; e += kSepThreads) {
-            int r = 0;
-            while (r < 4 && e >= base[r + 1]) ++r;
-            const int q = e - base[r];
-            double sn, cs;
-            sincospi(-2.0 * q / (double)rad[r], &sn, &cs);
-            wr[e] = make_float2((float)cs, (float)sn);
-        }
-    }
+    // twiddles of every pass and the roots of unity of every radix, from the
+    // context's table (tw and wr are contiguous, as in the table)
+    for (int e = t; e < g.n_tw + 21; e += kSepThreads) tw[e] = g.twt[e];
     const float2 *src = P + (size_t)plane * g.F * g.npix + px0;
     const int npx = min(kSepPix, g.npix - px0);
     for (int e = t; e < g.F * kSepPix; e += kSepThreads) {
@@ -253,6 +239,7 @@ static bool sep_factor(int F, SepArgs &g) {
             if (g.n_pass == kSepMaxPass) return false;
             g.radix[g.n_pass] = r;
             g.tw_off[g.n_pass] = off;
+            g.pmag[g.n_pass] = p == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)p + 1ull);
             off += p * r;
             p *= r;
             ++g.n_pass;
@@ -266,6 +253,34 @@ static bool sep_factor(int F, SepArgs &g) {
 bool separate_supported(int F) {
     SepArgs g;
     return F >= 2 && F <= kSepMaxFrames && sep_factor(F, g);
+}
+
+// The kernel's table for F frames: tw[tw_off[s] + k R + q] = exp(-2 pi i q k /
+// (p R)) for every pass s (radix R, p = product of the earlier radices), then
+// the roots exp(-2 pi i q / R) of R = 2, 3, 4, 5, 7 (2 + 3 + 4 + 5 + 7 = 21
+// entries); FP64, rounded to FP32.  Empty if F is not supported.
+std::vector<float2> separate_twiddles(int F) {
+    SepArgs g;
+    if (!separate_supported(F)) return {};
+    sep_factor(F, g);
+    std::vector<float2> t((size_t)g.n_tw + 21);
+    auto root = [](double turns) {      // exp(2 pi i turns)
+        return make_float2((float)std::cos(2.0 * M_PI * turns), (float)std::sin(2.0 * M_PI * turns));
+    };
+    int p = 1;
+    for (int s = 0; s < g.n_pass; ++s) {
+        const int R = g.radix[s];
+        for (int e = 0; e < p * R; ++e) {
+            const int k = e / R, q = e % R;
+            t[g.tw_off[s] + e] = root(-(double)((long)q * k % (p * R)) / (double)(p * R));
+        }
+        p *= R;
+    }
+    const int rad[5] = {2, 3, 4, 5, 7};
+    int o = g.n_tw;
+    for (int r : rad)
+        for (int q = 0; q < r; ++q) t[o++] = root(-(double)q / (double)r);
+    return t;
 }
 
 size_t separate_lds_bytes(int F) {
@@ -290,6 +305,8 @@ hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, flo
             g.lo[d * n_speed + s] = 1 + (s * g.H) / n_speed;
             g.hi[d * n_speed + s] = 1 + ((s + 1) * g.H) / n_speed;
         }
+    g.twt = ctx->tab.sep_tw;
+    if (!g.twt) return hipErrorInvalidValue;
     const int groups = cdiv(g.npix, kSepPix);
     hipLaunchKernelGGL(sep_kernel, dim3(groups * g.planes), dim3(kSepThreads),
                        separate_lds_bytes(g.F), st, P, out, g);

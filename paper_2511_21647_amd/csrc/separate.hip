@@ -4,9 +4,9 @@
 // negative ones, H = (F - 1) / 2, each direction split by |frequency| into S
 // contiguous speed ranges), and the inverse DFT of each masked spectrum.
 //
-// sep_kernel: one work-group per (plane, 16 consecutive pixels).  The frames
+// sep_kernel: one work-group per (plane, 8 consecutive pixels).  The frames
 // of those pixels are staged in LDS ([frame][pixel], pixels fastest, so the
-// global loads and stores are 128-byte rows and the butterflies read
+// global loads and stores are 64-byte rows and the butterflies read
 // consecutive banks), transformed by a mixed-radix Stockham FFT (radices 4, 2,
 // 3, 5, 7) that ping-pongs between two LDS buffers, and the spectrum is kept in
 // registers; each subset then rewrites its masked spectrum to LDS, runs the
@@ -21,7 +21,7 @@
 
 namespace ulm {
 
-constexpr int kSepPix = 16;                 // pixels per work-group
+constexpr int kSepPix = 8;                  // pixels per work-group
 constexpr int kSepThreads = 256;
 constexpr int kSepMaxFrames = 512;
 constexpr int kSepMaxPass = 12;

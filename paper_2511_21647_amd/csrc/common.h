@@ -89,7 +89,7 @@ struct Workspace {
 template <typename T> __host__ __device__ inline T cdiv(T a, T b) { return (a + b - 1) / b; }
 
 // Columns of the padded clutter subspace the removal kernel is compiled for.
-inline int removal_cols(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 16 ? 16 : c <= 24 ? 24 : 32; }
+inline int removal_cols(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 12 ? 12 : c <= 16 ? 16 : c <= 20 ? 20 : c <= 24 ? 24 : 32; }
 
 // Work-group remap so that consecutive logical work-groups land on the same
 // XCD (the dispatcher deals work-groups round-robin over the 8 XCDs), so

@@ -735,7 +735,9 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         switch (CM) {
             case 4: hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
             case 8: hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            case 12: hipLaunchKernelGGL(removal_kernel<12>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
             case 16: hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+            case 20: hipLaunchKernelGGL(removal_kernel<20>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
             case 24: hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
             default: hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
         }

@@ -155,6 +155,53 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     return ms_step, stage, n_det
 
 
+def run_inflight(cfg, ctx, iq, args):
+    """Throughput of the plain path with `args.inflight` ensembles in flight: each
+    has its own context (tables and workspace) and HIP stream, and consecutive
+    ensembles alternate between them, so one ensemble's latency-bound kernels
+    (the eigensolver holds one XCD per plane) overlap the next one's DAS.
+    Returns (ms per ensemble, detections of the last ensemble per context)."""
+    import torch
+    import paper_2511_21647_amd as ulm
+
+    n = args.inflight
+    cap = 4_000_000
+    ctxs = [ctx] + [ulm.Context(cfg) for _ in range(n - 1)]
+    streams = [torch.cuda.Stream() for _ in range(n)]
+    bufs = [dict(proj=torch.empty(ctx.proj_shape, dtype=torch.complex64, device="cuda"),
+                 eig=torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device="cuda"),
+                 locs=torch.empty((cap, 8), dtype=torch.int32, device="cuda"),
+                 count=torch.zeros(1, dtype=torch.int32, device="cuda")) for _ in range(n)]
+    torch.cuda.synchronize()
+
+    def step(k):
+        i = k % n
+        c, b = ctxs[i], bufs[i]
+        with torch.cuda.stream(streams[i]):
+            ulm.rca_beamform_stage1(c, iq)
+            ulm.rca_beamform_stage2(c, b["proj"])
+            ulm.svd_clutter_filter(c, b["proj"], b["eig"])
+            ulm.ncc_localize(c, b["proj"], cap, b["locs"], b["count"])
+
+    for k in range(max(args.warmup, n)):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dets = []
+    for c, b in zip(ctxs, bufs):
+        ulm.ulm_check_status(c, b["count"], cap)
+        dets.append(int(b["count"].item()))
+    for c in ctxs[1:]:
+        c.close()
+    del bufs
+    torch.cuda.empty_cache()
+    return (t1 - t0) * 1e3 / args.steps, dets
+
+
 MOTION_MAX_LAG = 8
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -240,6 +287,13 @@ def run_gpu(args):
                                                                        stage.items()},
                       "detections": n}
     log(f"plain: {ms:.2f} ms/ensemble {stage}")
+    if args.inflight > 1:
+        ms_i, dets = run_inflight(cfg, ctx, iq, args)
+        if any(d != n for d in dets):
+            raise SystemExit(f"in-flight run found {dets} detections, the single run {n}")
+        forms["plain"]["inflight"] = {"ensembles_in_flight": args.inflight,
+                                      "ms_per_ensemble": round(ms_i, 3)}
+        log(f"plain, {args.inflight} ensembles in flight: {ms_i:.2f} ms/ensemble")
     forms["plain"]["motion_estimation"] = time_motion(cfg, ctx, args)
     log(f"motion estimation: {forms['plain']['motion_estimation']}")
     forms["plain"]["mb_separation"] = time_separation(cfg, ctx, args)
@@ -507,6 +561,8 @@ def main():
     ap.add_argument("--profile-das", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--stream", type=int, default=0, metavar="N")
+    ap.add_argument("--inflight", type=int, default=2, metavar="N",
+                    help="also time the plain path with N ensembles in flight on N streams")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)

@@ -56,8 +56,7 @@ struct Tables {
 };
 
 // Words per plane of the eigensolver's barrier area: one grid-barrier flag per
-// work-group (at most 32), and in the last word a record of whether every
-// work-group of the plane runs on the XCD its slot was dealt to.
+// work-group (at most 32).
 constexpr int kBarStride = 64;
 
 // Offsets of the workspace regions, in bytes.
@@ -75,7 +74,7 @@ struct Workspace {
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
     size_t vbuf, pbuf;  // [planes][2][F] c128      column / p exchange (by step parity)
-    size_t bar;         // [planes][kBarStride] i32 grid-barrier flags + XCD-placement word
+    size_t bar;         // [planes][kBarStride] i32 grid-barrier flags
     size_t eflag;       // [planes] i32
     size_t fmax;        // [planes][F] f32
     size_t band_cnt;    // [planes][F][bands] i32

@@ -7,7 +7,6 @@
 namespace ulm {
 
 constexpr int kCoopMaxW = 32;      // work-groups per plane (one barrier flag each)
-constexpr int kPlaceWord = kBarStride - 1;  // per-plane word: a work-group off its XCD
 
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)
@@ -21,11 +20,10 @@ struct EigArgs {
     double2 *xscr;      // [planes][c][F]
     double2 *vbuf;      // [planes][2][F] published columns (double-buffered by step parity)
     double2 *pbuf;      // [planes][2][F] published p = tau A v
-    int *bar;           // [planes][kBarStride] barrier flags, then the XCD-placement word; zero at launch
+    int *bar;           // [planes][kBarStride] barrier flags, zero at launch
     int *flag;          // [planes] non-finite input
     int *status;
     int F, c, W;
-    int agent_scope;    // nonzero: agent-scope stores even on a single XCD
     int planes;         // solve planes [plane0, planes)
     int plane0;
 };

@@ -78,14 +78,14 @@ __device__ inline double bmax(double v, double *red) {
     return s;
 }
 
-// Cross-work-group loads are relaxed agent-scope atomics: loads with the
-// device-coherence bit, which miss the CU's L1 and read the L2.  A work-group
-// arrives at a barrier only after its own stores have completed (s_waitcnt 0).
-// Stores come in two kinds.  When every work-group of a plane runs on one XCD
-// (checked at launch from the hardware XCC id), they all share that XCD's L2,
-// and plain stores, complete once they reach it, are enough: this is the
-// "local" mode, and it shortens every barrier.  Otherwise stores are
-// agent-scope atomics too, which write through to memory.
+// Cross-work-group traffic uses relaxed agent-scope atomic loads and stores:
+// a store is complete only once it has reached the device's coherence point,
+// and a load reads from there, so data and barrier flags exchanged this way
+// are seen in the order they were written, whichever XCDs the work-groups run
+// on.  A work-group arrives at a barrier only after its own stores have
+// completed (s_waitcnt 0).  (Plain stores are faster, complete once they reach
+// the XCD's L2, but with other kernels running at the same time a barrier flag
+// written that way was seen before the data written ahead of it.)
 __device__ inline void st_c(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -99,29 +99,14 @@ __device__ inline void st_c2(double2 *p, double2 v) {
 __device__ inline double2 ld_c2(const double2 *p) {
     return make_double2(ld_c((const double *)p), ld_c((const double *)p + 1));
 }
-__device__ inline void put(double *p, double v, bool local) {
-    if (local) *p = v;
-    else st_c(p, v);
-}
-__device__ inline void put2(double2 *p, double2 v, bool local) {
-    if (local) *p = v;
-    else st_c2(p, v);
-}
-// The XCC (XCD) this wave runs on.
-__device__ inline int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xf); }
-
 // Grid barrier among the W work-groups of one plane: work-group w publishes
 // the number of barriers it has reached in its own flag, and lanes 0..W-1 of
 // the first wave each wait for one work-group's flag, so no single counter is
 // contended.  Returns false if the wait timed out (the caller then exits).
-__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status,
-                                     bool local = false) {
+__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (local) flags[w] = step;
-        else __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)threadIdx.x < W) {
         int spins = 0;
         while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
@@ -215,12 +200,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     bad = bmax(bad, red);
     if (t == 0 && bad > 0.0) atomicOr(a.flag + plane, 1);
-    // work-group slot g is meant to run on XCD g mod 8, like every slot of its
-    // plane; one that does not switches the plane to agent-scope stores
-    if (t == 0 && xcc_id() != xcd) atomicOr(flags + kPlaceWord, 1);
-    // the owner of column 0 publishes it
+    // the owner of column 0 publishes it, in the odd-step half of the exchange
+    // area: step 0 writes column 1 into the even half while a work-group that
+    // passed the first barrier late may still be reading column 0
     if (w == 0)
-        for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + i, Acol[i]);
+        for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + F + i, Acol[i]);
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
     if (__hip_atomic_load(a.flag + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         if (w == 0) {
@@ -234,13 +218,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         }
         return;
     }
-    const bool local =
-        !a.agent_scope && __hip_atomic_load(flags + kPlaceWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     // thread t owns rows t + 256 m of the column being reduced (scol) and of
     // sv, sp; nrm_part is its share of the next reflector's |x|^2
     double nrm_part = 0.0;
     for (int i = t; i < F; i += kCoopThreads) {
-        const double2 x = ld_c2(cbuf + i);
+        const double2 x = ld_c2(cbuf + F + i);
         scol[i] = x;
         if (i >= 2) nrm_part += x.x * x.x + x.y * x.y;
     }
@@ -254,11 +236,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         reflector(scol, k, F, red, svn, tk, beta, nrm_part);
         __syncthreads();
         if (w == k % W) {
-            for (int i = k + 1 + t; i < F; i += kCoopThreads) put2(H + (size_t)k * F + i, svn[i], local);
+            for (int i = k + 1 + t; i < F; i += kCoopThreads) st_c2(H + (size_t)k * F + i, svn[i]);
             if (t == 0) {
-                put(d + k, scol[k].x, local);
-                put(e + k, beta, local);
-                put2(tau + k, tk, local);
+                st_c(d + k, scol[k].x);
+                st_c(e + k, beta);
+                st_c2(tau + k, tk);
             }
         }
         // own columns j > k: pending update, then p_j = tau_k sum_i conj(A[i][j]) v_i
@@ -281,11 +263,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             ar = wsum(ar);
             ai = wsum(ai);
             const double2 pj = cmul2(tk, make_double2(ar, ai));
-            if (lane == 0) put2(pbuf + par * F + j, pj, local);
+            if (lane == 0) st_c2(pbuf + par * F + j, pj);
             if (j == k + 1)    // publish the next column (rows > k) for every work-group
-                for (int i = k + 1 + lane; i < F; i += 64) put2(cbuf + par * F + i, col[i], local);
+                for (int i = k + 1 + lane; i < F; i += 64) st_c2(cbuf + par * F + i, col[i]);
         }
-        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
+        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
         // every work-group reads all of p and the next column, forms p^H v itself
         // and applies the update of step k to column k+1 (rows > k)
         constexpr int kOwn = 64 * kCoopRows / kCoopThreads;     // rows per thread: F <= 512
@@ -333,11 +315,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     // last diagonal entry: column F-1 with the update of step F-2 applied
     __syncthreads();
     if (w == 0 && t == 0) {
-        put(d + F - 1, scol[F - 1].x, local);
-        put(e + F - 1, 0.0, local);
-        put2(tau + F - 1, make_double2(0.0, 0.0), local);
+        st_c(d + F - 1, scol[F - 1].x);
+        st_c(e + F - 1, 0.0);
+        st_c2(tau + F - 1, make_double2(0.0, 0.0));
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 2. every eigenvalue by multisection on Sturm counts: one wave per
     //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
@@ -408,11 +390,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             }
         }
         if (mine && pi == 0) {
-            put(lam + idx, 0.5 * (lo + hi), local);
+            st_c(lam + idx, 0.5 * (lo + hi));
             if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
         }
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
     if (c <= 0) return;
 
     // 3. inverse iteration for eigenvector vi of T (the vi-th largest
@@ -498,11 +480,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 for (int i = 0; i < F; ++i) y[i] *= inv;
             }
             double *yo = ts + (size_t)vi * 6 * F + 4 * F;
-            for (int i = 0; i < F; ++i) put(yo + i, y[i], local);
+            for (int i = 0; i < F; ++i) st_c(yo + i, y[i]);
         }
         __syncthreads();
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 4. work-group 0: two passes of classical Gram-Schmidt over the c vectors
     //    (staged in LDS), then normalise
@@ -539,9 +521,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             __syncthreads();
         }
         for (int i = t; i < c * F; i += kCoopThreads)
-            put(ts + (size_t)(i / F) * 6 * F + 4 * F + (i % F), Y[i], local);
+            st_c(ts + (size_t)(i / F) * 6 * F + 4 * F + (i % F), Y[i]);
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, local)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
 
     // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
     //    x held in registers (lane owns rows lane + 64 m), the next two

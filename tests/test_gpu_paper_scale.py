@@ -91,6 +91,42 @@ def test_paper_filter_full_planes(torch, ulm, cfg):
         del ctx, d
 
 
+def test_paper_two_streams_match_one(torch, ulm, cfg):
+    """Two contexts on two HIP streams, consecutive paper-scale ensembles
+    alternating between them (the eigensolver of one runs beside the other's
+    DAS): every context's beamformed-and-filtered planes and eigenvalues equal,
+    bit for bit, those of one context running alone."""
+    gen = torch.Generator(device="cuda").manual_seed(77)
+    ctx0 = ulm.Context(cfg)
+    iq = torch.randn(ctx0.iq_shape, dtype=torch.complex64, device="cuda", generator=gen)
+    shape = ctx0.proj_shape
+
+    def run(ctx, proj, eig):
+        ulm.rca_beamform_stage1(ctx, iq)
+        ulm.rca_beamform_stage2(ctx, proj)
+        ulm.svd_clutter_filter(ctx, proj, eig)
+
+    ref = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    ref_eig = torch.empty(shape[:3], dtype=torch.float64, device="cuda")
+    run(ctx0, ref, ref_eig)
+    torch.cuda.synchronize()
+    ulm.ulm_check_status(ctx0)
+    ctxs = [ctx0, ulm.Context(cfg)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [(torch.empty_like(ref), torch.empty_like(ref_eig)) for _ in range(2)]
+    for rnd in range(3):
+        for k in range(6):
+            i = k % 2
+            with torch.cuda.stream(streams[i]):
+                run(ctxs[i], *outs[i])
+        torch.cuda.synchronize()
+        for i in range(2):
+            ulm.ulm_check_status(ctxs[i])
+            same = bool(torch.equal(outs[i][0], ref)) and bool(torch.equal(outs[i][1], ref_eig))
+            say(f"[two streams] round {rnd} context {i}: identical to the lone run: {same}")
+            assert same
+
+
 def _spot_frames(F, nz, nu, frames, seed):
     """Filtered-plane stand-ins: isolated Gaussian spots with random phase and a
     weak noise floor in the sampled frames, zeros elsewhere."""

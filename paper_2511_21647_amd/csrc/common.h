@@ -56,7 +56,8 @@ struct Tables {
 };
 
 // Words per plane of the eigensolver's barrier area: one grid-barrier flag per
-// work-group (at most 32).
+// work-group (at most 32), and in the last word the set of XCDs (XCC ids) the
+// plane's work-groups run on.
 constexpr int kBarStride = 64;
 
 // Offsets of the workspace regions, in bytes.
@@ -74,7 +75,7 @@ struct Workspace {
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors
     size_t vbuf, pbuf;  // [planes][2][F] c128      column / p exchange (by step parity)
-    size_t bar;         // [planes][kBarStride] i32 grid-barrier flags
+    size_t bar;         // [planes][kBarStride] i32 grid-barrier flags + XCC mask
     size_t eflag;       // [planes] i32
     size_t fmax;        // [planes][F] f32
     size_t band_cnt;    // [planes][F][bands] i32

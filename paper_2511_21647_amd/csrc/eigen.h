@@ -7,6 +7,7 @@
 namespace ulm {
 
 constexpr int kCoopMaxW = 32;      // work-groups per plane (one barrier flag each)
+constexpr int kPlaceWord = kBarStride - 1;  // per-plane word: bit x set by a work-group on XCC x
 
 struct EigArgs {
     const double2 *C;   // [planes][F][F] covariance (full Hermitian)
@@ -20,10 +21,11 @@ struct EigArgs {
     double2 *xscr;      // [planes][c][F]
     double2 *vbuf;      // [planes][2][F] published columns (double-buffered by step parity)
     double2 *pbuf;      // [planes][2][F] published p = tau A v
-    int *bar;           // [planes][kBarStride] barrier flags, zero at launch
+    int *bar;           // [planes][kBarStride] barrier flags and the XCC mask, zero at launch
     int *flag;          // [planes] non-finite input
     int *status;
     int F, c, W;
+    int agent_scope;    // nonzero: the fenced mode even when a plane is on one XCD
     int planes;         // solve planes [plane0, planes)
     int plane0;
 };

@@ -78,14 +78,23 @@ __device__ inline double bmax(double v, double *red) {
     return s;
 }
 
-// Cross-work-group traffic uses relaxed agent-scope atomic loads and stores:
-// a store is complete only once it has reached the device's coherence point,
-// and a load reads from there, so data and barrier flags exchanged this way
-// are seen in the order they were written, whichever XCDs the work-groups run
-// on.  A work-group arrives at a barrier only after its own stores have
-// completed (s_waitcnt 0).  (Plain stores are faster, complete once they reach
-// the XCD's L2, but with other kernels running at the same time a barrier flag
-// written that way was seen before the data written ahead of it.)
+// Cross-work-group traffic.  A plane's work-groups are dealt to one XCD when
+// the kernel runs alone; kernels running at the same time on other streams
+// shift the dispatcher's XCD rotation and can split a plane over XCDs, whose
+// L2s are not coherent with each other.  Each work-group therefore sets its
+// hardware XCC id's bit in a per-plane mask at system scope before the first
+// grid barrier (which also runs at system scope), and the plane then runs in
+// one of two modes:
+//  - local: every work-group on one XCD.  They share its L2: plain stores,
+//    complete once they reach it, and agent-scope loads (which miss the CU's
+//    L1 and read the L2) exchange the data, and a barrier is a plain flag
+//    store and an agent-scope poll.
+//  - fenced: the plane spans XCDs.  Stores and loads are agent-scope atomics,
+//    and every barrier is a release fence (L2 write-back) before a
+//    system-scope flag store and an acquire fence (cache invalidation) after
+//    a system-scope poll.
+// A work-group arrives at a barrier only after its own stores have completed
+// (s_waitcnt 0).
 __device__ inline void st_c(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -99,17 +108,51 @@ __device__ inline void st_c2(double2 *p, double2 v) {
 __device__ inline double2 ld_c2(const double2 *p) {
     return make_double2(ld_c((const double *)p), ld_c((const double *)p + 1));
 }
+__device__ inline void put(double *p, double v, bool local) {
+    if (local) *p = v;
+    else st_c(p, v);
+}
+__device__ inline void put2(double2 *p, double2 v, bool local) {
+    if (local) *p = v;
+    else st_c2(p, v);
+}
+// The XCC (XCD) this wave runs on.
+__device__ inline int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xf); }
+__device__ inline void st_sys2(double2 *p, double2 v) {
+    __hip_atomic_store((double *)p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store((double *)p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline double2 ld_sys2(const double2 *p) {
+    return make_double2(
+        __hip_atomic_load(const_cast<double *>((const double *)p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+        __hip_atomic_load(const_cast<double *>((const double *)p + 1), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_SYSTEM));
+}
+enum BarMode { kBarSystem, kBarFenced, kBarLocal };
 // Grid barrier among the W work-groups of one plane: work-group w publishes
 // the number of barriers it has reached in its own flag, and lanes 0..W-1 of
 // the first wave each wait for one work-group's flag, so no single counter is
 // contended.  Returns false if the wait timed out (the caller then exits).
-__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status) {
+__device__ inline int load_flag(const int *p, BarMode mode) {
+    int *q = const_cast<int *>(p);
+    return mode == kBarLocal ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *abort_s, int *status,
+                                     BarMode mode) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        if (mode == kBarLocal) {
+            flags[w] = step;
+        } else {
+            if (mode == kBarFenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(flags + w, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
     if ((int)threadIdx.x < W) {
         int spins = 0;
-        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
+        while (load_flag(flags + threadIdx.x, mode) < step) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1 << 23)) {
                 *abort_s = 1;
@@ -119,6 +162,7 @@ __device__ inline bool plane_barrier(int *flags, int w, int W, int step, int *ab
         }
     }
     __syncthreads();
+    if (mode == kBarFenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *abort_s == 0;
 }
 
@@ -199,14 +243,18 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         scol[i] = make_double2(0.0, 0.0);
     }
     bad = bmax(bad, red);
-    if (t == 0 && bad > 0.0) atomicOr(a.flag + plane, 1);
+    if (t == 0) {
+        if (bad > 0.0) __hip_atomic_fetch_or(a.flag + plane, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_fetch_or(flags + kPlaceWord, 1 << xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     // the owner of column 0 publishes it, in the odd-step half of the exchange
     // area: step 0 writes column 1 into the even half while a work-group that
-    // passed the first barrier late may still be reading column 0
+    // passed the first barrier late may still be reading column 0.  This first
+    // exchange and barrier run at system scope: the mode is not known yet.
     if (w == 0)
-        for (int i = t; i < F; i += kCoopThreads) st_c2(cbuf + F + i, Acol[i]);
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
-    if (__hip_atomic_load(a.flag + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        for (int i = t; i < F; i += kCoopThreads) st_sys2(cbuf + F + i, Acol[i]);
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, kBarSystem)) return;
+    if (__hip_atomic_load(a.flag + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
         if (w == 0) {
             double2 *V = a.V + (size_t)plane * F * (c > 0 ? c : 1);
             for (int i = t; i < F * c; i += kCoopThreads) V[i] = make_double2(0.0, 0.0);
@@ -218,11 +266,15 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         }
         return;
     }
+    const unsigned xccs =
+        (unsigned)__hip_atomic_load(flags + kPlaceWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const bool local = !a.agent_scope && __popc(xccs) == 1;
+    const BarMode bmode = local ? kBarLocal : kBarFenced;
     // thread t owns rows t + 256 m of the column being reduced (scol) and of
     // sv, sp; nrm_part is its share of the next reflector's |x|^2
     double nrm_part = 0.0;
     for (int i = t; i < F; i += kCoopThreads) {
-        const double2 x = ld_c2(cbuf + F + i);
+        const double2 x = ld_sys2(cbuf + F + i);
         scol[i] = x;
         if (i >= 2) nrm_part += x.x * x.x + x.y * x.y;
     }
@@ -236,11 +288,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
         reflector(scol, k, F, red, svn, tk, beta, nrm_part);
         __syncthreads();
         if (w == k % W) {
-            for (int i = k + 1 + t; i < F; i += kCoopThreads) st_c2(H + (size_t)k * F + i, svn[i]);
+            for (int i = k + 1 + t; i < F; i += kCoopThreads) put2(H + (size_t)k * F + i, svn[i], local);
             if (t == 0) {
-                st_c(d + k, scol[k].x);
-                st_c(e + k, beta);
-                st_c2(tau + k, tk);
+                put(d + k, scol[k].x, local);
+                put(e + k, beta, local);
+                put2(tau + k, tk, local);
             }
         }
         // own columns j > k: pending update, then p_j = tau_k sum_i conj(A[i][j]) v_i
@@ -263,11 +315,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             ar = wsum(ar);
             ai = wsum(ai);
             const double2 pj = cmul2(tk, make_double2(ar, ai));
-            if (lane == 0) st_c2(pbuf + par * F + j, pj);
+            if (lane == 0) put2(pbuf + par * F + j, pj, local);
             if (j == k + 1)    // publish the next column (rows > k) for every work-group
-                for (int i = k + 1 + lane; i < F; i += 64) st_c2(cbuf + par * F + i, col[i]);
+                for (int i = k + 1 + lane; i < F; i += 64) put2(cbuf + par * F + i, col[i], local);
         }
-        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+        if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
         // every work-group reads all of p and the next column, forms p^H v itself
         // and applies the update of step k to column k+1 (rows > k)
         constexpr int kOwn = 64 * kCoopRows / kCoopThreads;     // rows per thread: F <= 512
@@ -315,11 +367,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     // last diagonal entry: column F-1 with the update of step F-2 applied
     __syncthreads();
     if (w == 0 && t == 0) {
-        st_c(d + F - 1, scol[F - 1].x);
-        st_c(e + F - 1, 0.0);
-        st_c2(tau + F - 1, make_double2(0.0, 0.0));
+        put(d + F - 1, scol[F - 1].x, local);
+        put(e + F - 1, 0.0, local);
+        put2(tau + F - 1, make_double2(0.0, 0.0), local);
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
 
     // 2. every eigenvalue by multisection on Sturm counts: one wave per
     //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
@@ -390,11 +442,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             }
         }
         if (mine && pi == 0) {
-            st_c(lam + idx, 0.5 * (lo + hi));
+            put(lam + idx, 0.5 * (lo + hi), local);
             if (a.lam_out) a.lam_out[(size_t)plane * F + idx] = 0.5 * (lo + hi);
         }
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
     if (c <= 0) return;
 
     // 3. inverse iteration for eigenvector vi of T (the vi-th largest
@@ -480,11 +532,11 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
                 for (int i = 0; i < F; ++i) y[i] *= inv;
             }
             double *yo = ts + (size_t)vi * 6 * F + 4 * F;
-            for (int i = 0; i < F; ++i) st_c(yo + i, y[i]);
+            for (int i = 0; i < F; ++i) put(yo + i, y[i], local);
         }
         __syncthreads();
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
 
     // 4. work-group 0: two passes of classical Gram-Schmidt over the c vectors
     //    (staged in LDS), then normalise
@@ -521,9 +573,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             __syncthreads();
         }
         for (int i = t; i < c * F; i += kCoopThreads)
-            st_c(ts + (size_t)(i / F) * 6 * F + 4 * F + (i % F), Y[i]);
+            put(ts + (size_t)(i / F) * 6 * F + 4 * F + (i % F), Y[i], local);
     }
-    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status)) return;
+    if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
 
     // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
     //    x held in registers (lane owns rows lane + 64 m), the next two

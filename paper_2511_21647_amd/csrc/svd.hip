@@ -12,6 +12,7 @@
 #include "eigen.h"
 
 #include <float.h>
+#include <stdlib.h>
 
 namespace ulm {
 
@@ -711,6 +712,9 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
         a.F = F;
         a.c = c;
         a.W = eigen_coop_width(F);
+        // diagnostic switch: the fenced exchange mode even where a plane's
+        // work-groups share one XCD (the results are the same bit for bit)
+        a.agent_scope = getenv("ULMPROJ_EIGEN_AGENT_SCOPE") != nullptr;
         a.planes = planes;
         a.plane0 = 0;
         if ((e = launch_eigen_coop(a, st)) != hipSuccess) return e;

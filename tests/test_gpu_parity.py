@@ -96,6 +96,32 @@ def test_filter_cutoff_zero_is_identity(torch, ulm):
     assert np.array_equal(d.cpu().numpy(), x)
 
 
+def test_filter_store_modes_agree(torch, ulm, monkeypatch):
+    """The eigensolver's two cross-work-group exchange modes (plain stores into
+    the shared L2 of one XCD; agent-scope stores with release and acquire
+    fences at every barrier) do the same arithmetic, so the filtered planes
+    and eigenvalues agree bit for bit."""
+    F, nz, nu, c = 130, 40, 37, 12
+    cfg = with_frames(cfg_tiny(), F)
+    cfg = cfg.with_(svd_cutoff=c, grid=replace(cfg.grid, nz=nz, nu=nu, nv=nu))
+    x = _filter_input(F, nz, nu, seed=310)
+    ctx = ulm.Context(cfg)
+    out = []
+    for fenced in (False, True):
+        if fenced:
+            monkeypatch.setenv("ULMPROJ_EIGEN_AGENT_SCOPE", "1")
+        else:
+            monkeypatch.delenv("ULMPROJ_EIGEN_AGENT_SCOPE", raising=False)
+        d = _to_dev(torch, x, torch.complex64)
+        ev = ulm.svd_clutter_filter(ctx, d)
+        ulm.ulm_check_status(ctx)
+        out.append((d.cpu().numpy(), ev.cpu().numpy()))
+    say(f"[filter exchange modes] F={F}: planes equal {np.array_equal(out[0][0], out[1][0])}, "
+        f"eigenvalues equal {np.array_equal(out[0][1], out[1][1])}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_filter_bf16x3_error(torch, ulm):
     """Split-precision form: states its error against the FP64 oracle."""
     F, nz, nu, c = 70, 64, 70, 3

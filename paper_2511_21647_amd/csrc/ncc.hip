@@ -32,7 +32,16 @@ __global__ __launch_bounds__(256) void frame_max_kernel(const float2 *__restrict
 {
     const float2 *src = P + (size_t)blockIdx.x * npix;
     float m = 0.f;
-    for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+    // eight loads in flight per thread (the launch is one work-group per image)
+    int i = threadIdx.x;
+    for (; i + 7 * 256 < npix; i += 8 * 256) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[i + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m = fmaxf(m, sqrtf(v[u].x * v[u].x + v[u].y * v[u].y));
+    }
+    for (; i < npix; i += 256) {
         const float2 v = src[i];
         m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y));
     }

@@ -31,7 +31,7 @@ namespace ulm {
 
 constexpr int kCoopThreads = 256;
 constexpr int kCoopWaves = kCoopThreads / 64;
-constexpr int kCoopRows = 8;     // back-transformation rows per lane: F <= 512
+constexpr int kCoopRows = 8;     // rows per lane of a 64-lane column: F <= 512
 constexpr int kPoints = 16;      // multisection points per eigenvalue and round
 constexpr int kGroups = 64 / kPoints;   // eigenvalues per wave: F <= kGroups x 4 waves x W
 
@@ -214,6 +214,7 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     double2 *scol = svn + F;                  // column k as published by its owner
     __shared__ double red[kCoopWaves];
     __shared__ double2 wpart[kCoopWaves];
+    __shared__ double2 wpart2[2][kCoopWaves];
     __shared__ int abort_s;
     if (t == 0) abort_s = 0;
 
@@ -577,67 +578,75 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
 
-    // 5. back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector,
-    //    x held in registers (lane owns rows lane + 64 m), the next two
-    //    reflectors prefetched while the current one is applied
+    // 5. back-transformation x = H_0 H_1 ... H_{F-2} y: work-group w forms
+    //    vectors w, w + W, ...; thread t holds rows t + 256 m of x, the wave sums
+    //    meet in LDS (double-buffered by step parity, one barrier per step), and
+    //    the Householder rows of the next three steps are in flight
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double2 *V = a.V + (size_t)plane * F * c;
-    for (int vi = w * kCoopWaves + wave; vi < c; vi += W * kCoopWaves) {
+    constexpr int kOwn = 64 * kCoopRows / kCoopThreads;     // rows per thread: F <= 512
+    int bpar = 0;
+    for (int vi = w; vi < c; vi += W) {
         const double *y = ts + (size_t)vi * 6 * F + 4 * F;
-        double2 x[kCoopRows], vc[kCoopRows], vn[kCoopRows];
+        double2 x[kOwn];
 #pragma unroll
-        for (int m = 0; m < kCoopRows; ++m) {
-            const int q = lane + 64 * m;
+        for (int m = 0; m < kOwn; ++m) {
+            const int q = t + kCoopThreads * m;
             x[m] = make_double2(q < F ? y[q] : 0.0, 0.0);
         }
-        auto fetch = [&](int k, double2 *v) {
+        auto fetch = [&](int k, double2 (&h)[kOwn], double2 &tk) {
+            tk = k >= 0 ? tau[k] : make_double2(0.0, 0.0);
 #pragma unroll
-            for (int m = 0; m < kCoopRows; ++m) {
-                const int q = lane + 64 * m;
-                v[m] = (q > k && q < F) ? H[(size_t)k * F + q] : make_double2(0.0, 0.0);
+            for (int m = 0; m < kOwn; ++m) {
+                const int q = t + kCoopThreads * m;
+                h[m] = (k >= 0 && q > k && q < F) ? H[(size_t)k * F + q] : make_double2(0.0, 0.0);
             }
         };
-        // reflectors k-1 and k-2 are in flight while k is applied (an L2 round
-        // trip is several steps of this loop)
-        double2 vn2[kCoopRows];
-        double2 tc = F >= 2 ? tau[F - 2] : make_double2(0.0, 0.0);
-        double2 tn1 = F >= 3 ? tau[F - 3] : make_double2(0.0, 0.0);
-        if (F >= 2) fetch(F - 2, vc);
-        if (F >= 3) fetch(F - 3, vn);
+        double2 h0[kOwn], h1[kOwn], h2[kOwn], h3[kOwn], t0, t1, t2, t3;
+        fetch(F - 2, h0, t0);
+        fetch(F - 3, h1, t1);
+        fetch(F - 4, h2, t2);
         for (int k = F - 2; k >= 0; --k) {
-            double2 tn2 = make_double2(0.0, 0.0);
-            if (k > 1) {
-                tn2 = tau[k - 2];
-                fetch(k - 2, vn2);
-            }
-            if (tc.x != 0.0 || tc.y != 0.0) {
+            fetch(k - 3, h3, t3);
+            if (t0.x != 0.0 || t0.y != 0.0) {          // the same for every thread
                 double sr = 0.0, si = 0.0;
 #pragma unroll
-                for (int m = 0; m < kCoopRows; ++m) {
-                    const double2 p = cjmul2(vc[m], x[m]);
+                for (int m = 0; m < kOwn; ++m) {
+                    const double2 p = cjmul2(h0[m], x[m]);
                     sr += p.x;
                     si += p.y;
                 }
                 sr = wsum(sr);
                 si = wsum(si);
-                const double2 s = cmul2(tc, make_double2(sr, si));
+                if (lane == 0) wpart2[bpar][wave] = make_double2(sr, si);
+                __syncthreads();
+                double2 tot = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int m = 0; m < kCoopRows; ++m) {
-                    const double2 p = cmul2(vc[m], s);
+                for (int i = 0; i < kCoopWaves; ++i) {
+                    tot.x += wpart2[bpar][i].x;
+                    tot.y += wpart2[bpar][i].y;
+                }
+                bpar ^= 1;
+                const double2 sc = cmul2(t0, tot);
+#pragma unroll
+                for (int m = 0; m < kOwn; ++m) {
+                    const double2 p = cmul2(h0[m], sc);
                     x[m] = make_double2(x[m].x - p.x, x[m].y - p.y);
                 }
             }
-            tc = tn1;
-            tn1 = tn2;
 #pragma unroll
-            for (int m = 0; m < kCoopRows; ++m) {
-                vc[m] = vn[m];
-                vn[m] = vn2[m];
+            for (int m = 0; m < kOwn; ++m) {
+                h0[m] = h1[m];
+                h1[m] = h2[m];
+                h2[m] = h3[m];
             }
+            t0 = t1;
+            t1 = t2;
+            t2 = t3;
         }
 #pragma unroll
-        for (int m = 0; m < kCoopRows; ++m) {
-            const int q = lane + 64 * m;
+        for (int m = 0; m < kOwn; ++m) {
+            const int q = t + kCoopThreads * m;
             if (q < F) V[(size_t)q * c + vi] = x[m];
         }
     }

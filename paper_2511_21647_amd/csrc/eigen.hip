@@ -2,8 +2,8 @@
 // covariance of the Casorati matrix is eigendecomposed and the eigenvectors of
 // the largest eigenvalues span the clutter subspace).
 //
-// eigen_coop_kernel: W work-groups per plane, all on one XCD (the plane's
-// grid slots are dealt to a single XCD), launched cooperatively.
+// eigen_coop_kernel: W work-groups per plane, launched cooperatively; the
+// plane's grid slots are dealt to one XCD (see the exchange modes below).
 //   1. Householder reduction to real tridiagonal form T = Q^H C Q (the
 //      unblocked Hermitian reduction).  Column j of C lives in the LDS of
 //      work-group j mod W for the whole reduction.  The rank-2 update of step
@@ -11,18 +11,18 @@
 //      and every work-group forms the reflector v_k itself from the published
 //      column k, so each step costs one grid barrier: after every work-group
 //      has published its part of p_k = tau_k A v_k and the owner of column k+1
-//      has published that column; every work-group then reads all of p and
-//      forms p^H v itself.
-//   2. Every eigenvalue of T by multisection on Sturm counts (a wave per
-//      eigenvalue, 64 points per round), spread over the plane's work-groups.
+//      has published that column; every work-group then reads all of p, forms
+//      p^H v itself and applies the step's update to column k+1.
+//   2. Every eigenvalue of T by multisection on Sturm counts (16 lanes per
+//      eigenvalue, 16 points per round), spread over the plane's work-groups.
 //   3. Inverse iteration (partial-pivoting tridiagonal LU in LDS) for the c
 //      largest eigenvalues, one eigenvector per work-group.
 //   4. Work-group 0: two Gram-Schmidt passes over the c vectors in LDS.
-//   5. Back-transformation x = H_0 H_1 ... H_{F-2} y, one wave per vector with
-//      x in registers.
-// Grid barriers spin on an agent-scope counter with a bounded wait: a work-
-// group that waits too long flags the status word and exits, so every wave
-// always finishes.
+//   5. Back-transformation x = H_0 H_1 ... H_{F-2} y, one work-group per
+//      vector with x in registers.
+// Grid barriers spin on per-work-group flags with a bounded wait: a work-group
+// that waits too long flags the status word and exits, so every wave always
+// finishes.
 #include "eigen.h"
 
 #include <float.h>
@@ -374,9 +374,9 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     }
     if (!plane_barrier(flags, w, W, ++nbar, &abort_s, a.status, bmode)) return;
 
-    // 2. every eigenvalue by multisection on Sturm counts: one wave per
-    //    eigenvalue, its 64 lanes count at 64 interior points of the bracket,
-    //    so each round narrows the bracket 65-fold
+    // 2. every eigenvalue by multisection on Sturm counts: a group of kPoints
+    //    lanes per eigenvalue counts at kPoints interior points of its bracket,
+    //    so each round narrows the bracket (kPoints + 1)-fold
     double *sd = (double *)lds2;
     double *se2 = sd + F;
     double *se = se2 + F;

@@ -55,6 +55,10 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
     __shared__ float2 lds[2 * kGramBlock][kGramStage + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi = wave >> 1, wj = wave & 1;
+    // in a diagonal block the lower-left quadrant mirrors the upper-right one
+    // (C is Hermitian, and the reduction reads it from there): its wave only
+    // stages pixels
+    const bool mirror = I == J && wi == 1 && wj == 0;
     const int kk = lane >> 4, r16 = lane & 15;
 
     f64x4 accr[2][2], acci[2][2];
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
         __syncthreads();
         if (p0 + kGramStage < px1) fetch(p0 + kGramStage);
 #pragma unroll 4
-        for (int step = 0; step < kGramStage / 2; ++step) {
+        for (int step = 0; step < (mirror ? 0 : kGramStage / 2); ++step) {
             const int pxl = step * 2 + (kk >> 1);
             const bool im = kk & 1;
             double a[2], br[2], bi[2];
@@ -221,7 +225,11 @@ __global__ void gram_reduce_kernel(const double2 *__restrict__ part, double2 *__
     const int plane = (int)(idx / ((size_t)F * F));
     const int f1 = (int)((idx / F) % F), f2 = (int)(idx % F);
     int a = f1, b = f2;
-    const bool swap = (f1 / kGramBlock) > (f2 / kGramBlock);
+    // blocks below the diagonal, and the lower-left quadrant of a diagonal
+    // block, are read from their mirror image
+    const bool swap = (f1 / kGramBlock) > (f2 / kGramBlock) ||
+                      ((f1 / kGramBlock) == (f2 / kGramBlock) && (f1 % kGramBlock) >= kGramBlock / 2 &&
+                       (f2 % kGramBlock) < kGramBlock / 2);
     if (swap) { a = f2; b = f1; }
     const int I = a / kGramBlock, J = b / kGramBlock;
     int pair = 0;

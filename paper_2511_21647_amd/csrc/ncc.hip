@@ -66,7 +66,10 @@ __device__ inline float subpix(float nm, float n0, float np) {
 }
 
 // Peak test, sub-pixel fit and raster-order compaction of one band, from the
-// band's NCC rows (with a halo row above and below) in LDS.
+// band's NCC rows (with a halo row above and below) in LDS.  Thread t tests the
+// raster run [t R, t R + R) of the band's pixels and counts its peaks; one
+// block-wide prefix sum of the counts gives every thread its output offset, so
+// the records come out in raster order with a single barrier.
 __device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
                             const float *__restrict__ fmax_in, ulm_loc_t *__restrict__ staged,
                             int *__restrict__ band_cnt, const NccParams &prm, int nz, int nu,
@@ -74,59 +77,82 @@ __device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
 {
     const int W_out = nu + 2;
     const int r0 = band * kNccBand;
-    // detection + raster-order compaction within the band
-    __shared__ int wave_tot[4];
-    __shared__ int base_s;
-    if (threadIdx.x == 0) base_s = 0;
+    __shared__ int wave_tot[16];
     const float thr_i = prm.alpha * fmax_in[plane * F + f];
     const int rows = min(kNccBand, nz - r0);
     const int npx = rows * nu;
     ulm_loc_t *out = staged + ((size_t)(plane * F + f) * bands + band) * band_cap;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int e0 = 0; e0 < npx; e0 += blockDim.x) {
-        const int e = e0 + threadIdx.x;
-        bool cand = false;
-        ulm_loc_t rec;
-        if (e < npx) {
-            const int rr = e / nu + 1, cc = e % nu + 1;      // position in the ncc array
-            const float n0 = ncc[rr * W_out + cc];
-            const int z = r0 + rr - 1, u = cc - 1;
-            if (n0 >= prm.tau) {
-                const float2 x = src[(size_t)z * nu + u];
-                const float I = sqrtf(x.x * x.x + x.y * x.y);
-                if (I >= thr_i) {
-                    const float *up = ncc + (rr - 1) * W_out + cc;
-                    const float *mid = ncc + rr * W_out + cc;
-                    const float *dn = ncc + (rr + 1) * W_out + cc;
-                    cand = n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] &&
-                           n0 >= mid[1] && n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
-                    if (cand) {
-                        const float dz = (z > 0 && z < nz - 1) ? subpix(up[0], n0, dn[0]) : 0.f;
-                        const float du = (u > 0 && u < nu - 1) ? subpix(mid[-1], n0, mid[1]) : 0.f;
-                        rec.plane = plane;
-                        rec.frame = f;
-                        rec.iz = z;
-                        rec.iu = u;
-                        rec.z = (float)z + dz;
-                        rec.u = (float)u + du;
-                        rec.ncc = n0;
-                        rec.intensity = I;
-                    }
-                }
-            }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    const int R = (npx + blockDim.x - 1) / blockDim.x;
+    const int e0 = min((int)threadIdx.x * R, npx), e1 = min(e0 + R, npx);
+
+    // 3x3 regional maximum (raster tie-break), NCC and intensity thresholds
+    auto is_peak = [&](int e, float &I) {
+        const int rr = e / nu + 1, cc = e % nu + 1;          // position in the ncc array
+        const float n0 = ncc[rr * W_out + cc];
+        if (!(n0 >= prm.tau)) return false;
+        const float2 x = src[(size_t)(r0 + rr - 1) * nu + (cc - 1)];
+        I = sqrtf(x.x * x.x + x.y * x.y);
+        if (!(I >= thr_i)) return false;
+        const float *up = ncc + (rr - 1) * W_out + cc;
+        const float *mid = ncc + rr * W_out + cc;
+        const float *dn = ncc + (rr + 1) * W_out + cc;
+        return n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] && n0 >= mid[1] &&
+               n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
+    };
+    unsigned long long mask = 0ull;                           // peaks among the run's first 64
+    int cnt = 0;
+    for (int e = e0; e < e1; ++e) {
+        float I;
+        if (is_peak(e, I)) {
+            if (e - e0 < 64) mask |= 1ull << (e - e0);
+            ++cnt;
         }
-        const unsigned long long bal = __ballot(cand);
-        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_tot[wv] = __popcll(bal);
-        __syncthreads();
-        int off = base_s;
-        for (int q = 0; q < wv; ++q) off += wave_tot[q];
-        if (cand) out[off + pre] = rec;
-        __syncthreads();
-        if (threadIdx.x == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-        __syncthreads();
     }
-    if (threadIdx.x == 0) band_cnt[(plane * F + f) * bands + band] = base_s;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wave_tot[wv] = incl;
+    __syncthreads();
+    int off = incl - cnt, total = 0;
+    for (int q = 0; q < nw; ++q) {
+        if (q < wv) off += wave_tot[q];
+        total += wave_tot[q];
+    }
+    auto emit = [&](int e, float I) {
+        const int rr = e / nu + 1, cc = e % nu + 1;
+        const int z = r0 + rr - 1, u = cc - 1;
+        const float *up = ncc + (rr - 1) * W_out + cc;
+        const float *mid = ncc + rr * W_out + cc;
+        const float *dn = ncc + (rr + 1) * W_out + cc;
+        const float n0 = mid[0];
+        const float dz = (z > 0 && z < nz - 1) ? subpix(up[0], n0, dn[0]) : 0.f;
+        const float du = (u > 0 && u < nu - 1) ? subpix(mid[-1], n0, mid[1]) : 0.f;
+        ulm_loc_t rec;
+        rec.plane = plane;
+        rec.frame = f;
+        rec.iz = z;
+        rec.iu = u;
+        rec.z = (float)z + dz;
+        rec.u = (float)u + du;
+        rec.ncc = n0;
+        rec.intensity = I;
+        out[off++] = rec;
+    };
+    while (mask) {
+        const int i = __ffsll((long long)mask) - 1;
+        mask &= mask - 1ull;
+        float I;
+        is_peak(e0 + i, I);                                   // recomputes I for the record
+        emit(e0 + i, I);
+    }
+    for (int e = e0 + 64; e < e1; ++e) {                      // runs longer than 64 pixels
+        float I;
+        if (is_peak(e, I)) emit(e, I);
+    }
+    if (threadIdx.x == 0) band_cnt[(plane * F + f) * bands + band] = total;
 }
 
 // Dynamic LDS: img [R_in][W_in] (reused for ncc [kNccBand+2][nu+2]), then

@@ -228,13 +228,14 @@ __global__ __launch_bounds__(256) void ncc_detect_kernel(
 }
 
 // Register-column form of the same computation, for images up to 512 - 2 - 2H
-// columns wide: thread t owns input columns t and t + 256 of the band and keeps
-// their 18 + 2H envelope values in registers; each output row's vertical sums go
-// through a small double-buffered LDS row, and the NCC rows of the band stay in
-// LDS for the peak test.  About 27 KB of LDS per work-group at the paper's width
-// (against ~91 KB for the staged form), so five work-groups share a CU.
+// columns wide, launched with one thread per input column (the block rounded
+// up to whole waves): thread t keeps column t's 18 + 2H envelope values in
+// registers; each output row's vertical sums go through a small
+// double-buffered LDS row, and the NCC rows of the band stay in LDS for the
+// peak test.  About 27 KB of LDS per work-group at the paper's width (against
+// ~91 KB for the staged form), so five work-groups share a CU.
 template <int H>
-__global__ __launch_bounds__(256) void ncc_band_kernel(
+__global__ __launch_bounds__(512) void ncc_band_kernel(
     const float2 *__restrict__ P, const float *__restrict__ fmax_in, ulm_loc_t *__restrict__ staged,
     int *__restrict__ band_cnt, NccParams prm, int nz, int nu, int F, int bands, int band_cap)
 {
@@ -250,11 +251,10 @@ __global__ __launch_bounds__(256) void ncc_band_kernel(
     const int r0 = band * kNccBand;
     const float2 *src = P + ((size_t)plane * F + f) * (size_t)nz * nu;
 
-    float col[2][R_in];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int cc = t + 256 * q, u = cc - 1 - H;
-        const bool cu = cc < W_in && u >= 0 && u < nu;
+    float col[R_in];
+    {
+        const int u = t - 1 - H;
+        const bool cu = t < W_in && u >= 0 && u < nu;
 #pragma unroll
         for (int rr = 0; rr < R_in; ++rr) {
             const int z = r0 - 1 - H + rr;
@@ -263,32 +263,28 @@ __global__ __launch_bounds__(256) void ncc_band_kernel(
                 const float2 x = src[(size_t)z * nu + u];
                 v = sqrtf(x.x * x.x + x.y * x.y);
             }
-            col[q][rr] = v;
+            col[rr] = v;
         }
     }
 #pragma unroll
     for (int rr = 0; rr < R_out; ++rr) {
         float *Vb = V + (rr & 1) * 3 * W_in;
+        if (t < W_in) {
+            float sg = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int cc = t + 256 * q;
-            if (cc < W_in) {
-                float sg = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-                for (int a = 0; a < S; ++a) {
-                    const float x = col[q][rr + a];
-                    sg = fmaf(prm.gz[a], x, sg);
-                    s1 += x;
-                    s2 = fmaf(x, x, s2);
-                }
-                Vb[cc] = sg;
-                Vb[W_in + cc] = s1;
-                Vb[2 * W_in + cc] = s2;
+            for (int a = 0; a < S; ++a) {
+                const float x = col[rr + a];
+                sg = fmaf(prm.gz[a], x, sg);
+                s1 += x;
+                s2 = fmaf(x, x, s2);
             }
+            Vb[t] = sg;
+            Vb[W_in + t] = s1;
+            Vb[2 * W_in + t] = s2;
         }
         __syncthreads();
         const int z = r0 - 1 + rr;
-        for (int co = t; co < W_out; co += 256) {
+        for (int co = t; co < W_out; co += blockDim.x) {
             const int u = co - 1;
             float out = -INFINITY;                  // outside the image: ignored by the peak test
             if (z >= 0 && z < nz && u >= 0 && u < nu) {
@@ -420,9 +416,10 @@ hipError_t launch_localize(const ulm_ctx *ctx, const float2 *filt, ulm_loc_t *lo
     const int W_in = g.nu + 2 + 2 * prm.half;
     if (W_in <= 512) {
         const size_t lds = (6 * (size_t)W_in + (size_t)(kNccBand + 2) * (g.nu + 2)) * sizeof(float);
+        const int threads = 64 * cdiv(W_in, 64);            // one per input column, <= 512
 #define ULM_NCC_BAND(HH)                                                                          \
     case HH:                                                                                      \
-        hipLaunchKernelGGL(ncc_band_kernel<HH>, grid, dim3(256), lds, st, filt, fmx, staged, bcnt, \
+        hipLaunchKernelGGL(ncc_band_kernel<HH>, grid, dim3(threads), lds, st, filt, fmx, staged, bcnt, \
                            prm, g.nz, g.nu, F, w.bands, w.band_cap);                              \
         break;
         switch (prm.half) {

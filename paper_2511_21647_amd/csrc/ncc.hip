@@ -86,19 +86,21 @@ __device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
     const int R = (npx + blockDim.x - 1) / blockDim.x;
     const int e0 = min((int)threadIdx.x * R, npx), e1 = min(e0 + R, npx);
 
-    // 3x3 regional maximum (raster tie-break), NCC and intensity thresholds
+    // NCC threshold, 3x3 regional maximum (raster tie-break), then the intensity
+    // threshold (its global read only for the few regional maxima)
     auto is_peak = [&](int e, float &I) {
         const int rr = e / nu + 1, cc = e % nu + 1;          // position in the ncc array
         const float n0 = ncc[rr * W_out + cc];
         if (!(n0 >= prm.tau)) return false;
-        const float2 x = src[(size_t)(r0 + rr - 1) * nu + (cc - 1)];
-        I = sqrtf(x.x * x.x + x.y * x.y);
-        if (!(I >= thr_i)) return false;
         const float *up = ncc + (rr - 1) * W_out + cc;
         const float *mid = ncc + rr * W_out + cc;
         const float *dn = ncc + (rr + 1) * W_out + cc;
-        return n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] && n0 >= mid[1] &&
-               n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1];
+        if (!(n0 > up[-1] && n0 > up[0] && n0 > up[1] && n0 > mid[-1] && n0 >= mid[1] &&
+              n0 >= dn[-1] && n0 >= dn[0] && n0 >= dn[1]))
+            return false;
+        const float2 x = src[(size_t)(r0 + rr - 1) * nu + (cc - 1)];
+        I = sqrtf(x.x * x.x + x.y * x.y);
+        return I >= thr_i;
     };
     unsigned long long mask = 0ull;                           // peaks among the run's first 64
     int cnt = 0;

@@ -181,10 +181,15 @@ __global__ __launch_bounds__(256) void mot_corr_kernel(const float2 *__restrict_
             const int pl = ph * 128 + 2 * st + hk;
             const float av = As[i32 * kMotAS + pl];
             const int base = (min(pz, rows - 1) + L) * W2 + pu + L;
+            // every tile slot runs (a slot past the last tile, odd NT only, reads
+            // the lag-0 value and is never stored), so the NH reads issue
+            // back to back ahead of their MFMAs
+            float bv[NH];
+#pragma unroll
+            for (int tt = 0; tt < NH; ++tt) bv[tt] = Bs[base - off[tt]];
 #pragma unroll
             for (int tt = 0; tt < NH; ++tt)
-                if (tt < nt_here)
-                    acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, Bs[base - off[tt]], acc[tt], 0, 0, 0);
+                acc[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[tt], acc[tt], 0, 0, 0);
             pu += 2;
             const bool wrap = pu >= a.nu;
             pu -= wrap ? a.nu : 0;

@@ -189,26 +189,44 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const T *__restrict__ in,
             }
         }
         __syncthreads();
-        f32x16 acc = {};
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
-            const T *arow = &tile[((wave + dy) * TC + i32 + dx) * PS];
-            const T *brow = &wl[i32 * WS + tap * kC];
-            if constexpr (sizeof(T) == 2) {
+        // two accumulation chains (the halves of each tap's channels), summed at
+        // the end, so consecutive MFMAs do not wait on each other's results
+        f32x16 acc2[2] = {{}, {}};
+        if constexpr (sizeof(T) == 2) {
+            // the next tap's operands are read while this tap's MFMAs run
+            bf16x8 av[2][2], bv[2][2];
+            auto fetch = [&](int tap, int slot) {
+                const int dy = tap / 3, dx = tap % 3;
+                const T *arow = &tile[((wave + dy) * TC + i32 + dx) * PS];
+                const T *brow = &wl[i32 * WS + tap * kC];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(arow + h * 16 + hk * 8);
-                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(brow + h * 16 + hk * 8);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+                    av[slot][h] = *reinterpret_cast<const bf16x8 *>(arow + h * 16 + hk * 8);
+                    bv[slot][h] = *reinterpret_cast<const bf16x8 *>(brow + h * 16 + hk * 8);
                 }
-            } else {
+            };
+            fetch(0, 0);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                if (tap + 1 < 9) fetch(tap + 1, (tap + 1) & 1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    acc2[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[tap & 1][h], bv[tap & 1][h], acc2[h],
+                                                                      0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                const T *arow = &tile[((wave + dy) * TC + i32 + dx) * PS];
+                const T *brow = &wl[i32 * WS + tap * kC];
 #pragma unroll
                 for (int s2 = 0; s2 < 16; ++s2)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * s2 + hk], brow[2 * s2 + hk],
-                                                               acc, 0, 0, 0);
+                    acc2[s2 & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * s2 + hk], brow[2 * s2 + hk],
+                                                                        acc2[s2 & 1], 0, 0, 0);
             }
         }
+        const f32x16 acc = acc2[0] + acc2[1];
         // lane holds D[8 (q / 4) + 4 hk + q % 4][i32]: pixel row of the tile, output channel i32;
         // the tile's LDS is reused to transpose the results (every wave is done reading it)
         __syncthreads();

@@ -462,6 +462,10 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
     double *__restrict__ sw = iu + F;
     double *__restrict__ y = sw + F;
     for (int vi = w; vi < c; vi += W) {
+        // the start vector, by every thread (the factor and solves below are
+        // serial recurrences, run by thread 0)
+        for (int i = t; i < F; i += kCoopThreads) y[i] = 1.0 + 0.37 * sin(0.731 * i + 1.3 * vi);
+        __syncthreads();
         if (t == 0) {
             const double lm = ld_c(lam + vi);
             const double tiny = DBL_EPSILON * tnorm + pivmin;
@@ -503,7 +507,6 @@ __global__ __launch_bounds__(kCoopThreads) void eigen_coop_kernel(EigArgs a)
             u1[F - 1] = 0.0;
             u2[F - 1] = 0.0;
             iu[F - 1] = 1.0 / c0;
-            for (int i = 0; i < F; ++i) y[i] = 1.0 + 0.37 * sin(0.731 * i + 1.3 * vi);
             for (int it = 0; it < 3; ++it) {
                 // forward: apply the row swaps and multipliers
                 double cur = y[0];

@@ -60,7 +60,7 @@ extern "C" {
 typedef struct ulm_config {
     /* probe: n_elem row elements and n_elem column elements */
     int32_t n_elem;
-    int32_t n_samp;       /* IQ samples per channel                          */
+    int32_t n_samp;       /* IQ samples per channel (at least 5)             */
     int32_t n_frames;     /* frames (volumes) per ensemble                   */
     int32_t n_angles;     /* plane-wave angles per orientation (<= 32)       */
     double  pitch;        /* element pitch, m                                */

@@ -84,7 +84,8 @@ static void free_tables(ulm_ctx *ctx) {
 }
 
 static int32_t validate(const ulm_config_t &c) {
-    if (c.n_elem < 1 || c.n_samp < 2 || c.n_frames < 1) return fail(ULM_ERR_INVALID_ARG, "n_elem, n_samp, n_frames");
+    // stage 1 reads runs of five samples of a record
+    if (c.n_elem < 1 || c.n_samp < 5 || c.n_frames < 1) return fail(ULM_ERR_INVALID_ARG, "n_elem, n_samp (at least 5), n_frames");
     if (c.n_angles < 1 || c.n_angles > ULM_MAX_ANGLES) return fail(ULM_ERR_INVALID_ARG, "n_angles out of [1, 32]");
     if (c.n_frames > 1024) return fail(ULM_ERR_INVALID_ARG, "n_frames > 1024");
     if (c.nu < 1 || c.nz < 1 || c.nv < 1 || c.n_blocks < 1 || c.n_blocks > c.nv)

@@ -73,51 +73,56 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     constexpr int NQ = FB * RUNS / kDasThreads;
     static_assert(NQ >= 1 && FB * RUNS % kDasThreads == 0, "staging map");
     // two register sets: the global loads of element j + 2 are in flight while
-    // element j is applied and element j + 1 (loaded one step earlier) is stored
-    float4 sa[NQ][4], sb[NQ][4];
-    float pa, pb;
-    float2 qa, qb;
-    auto load = [&](int j, float4 (&st)[NQ][4], float &prx, float2 &pph) {
+    // element j is applied and element j + 1 (loaded one step earlier) is stored.
+    // The loads write their registers unconditionally (start clamped into the
+    // record), so nothing waits on them before the store; a window that crosses
+    // an end of the record is read again, sample by sample with zeros outside,
+    // at the store.
+    float2 sa[NQ][5], sb[NQ][5];
+    auto row_of = [&](int j, int q) {
+        const int fl = das_frame<RUNS>(t + q * kDasThreads);
+        // frames past the end read the last frame; their sums are never written
+        return blk + (size_t)j * g.n_samp + (size_t)min(f0 + fl, g.n_frames - 1) * frame_stride;
+    };
+    auto load = [&](int j, float2 (&st)[NQ][5]) {
         const int s_lo = wj[j];
-        const float2 *ch = blk + (size_t)j * g.n_samp;
-        // the whole window (and the sample after it) inside the record: the same
-        // answer for every thread, so the branch below does not diverge
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int run = das_run<RUNS>(t + q * kDasThreads);
+            const float2 *row = row_of(j, q);
+            const int gs = max(min(s_lo + 4 * run, g.n_samp - 5), 0);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) st[q][i] = row[gs + i];
+        }
+    };
+    // the registers hold the five raw samples until the store, which forms the
+    // four (sample, difference) entries.  A window that crosses an end of the
+    // record (a uniform branch) is read again at the store, sample by sample
+    // with zeros outside the record, and those values are written instead.
+    auto store = [&](int b, int j, int s_lo, const float2 (&st)[NQ][5]) {
         const bool inside = s_lo >= 0 && s_lo + LEN < g.n_samp;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kDasThreads;
             const int fl = das_frame<RUNS>(e), run = das_run<RUNS>(e);
-            const int f = f0 + fl;
-            const float2 *row = ch + (size_t)min(f, g.n_frames - 1) * frame_stride;
-            const int gs = s_lo + 4 * run;
             float2 x[5];
             if (inside) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) x[i] = row[gs + i];
+                for (int i = 0; i < 5; ++i) x[i] = st[q][i];
             } else {
+                const float2 *row = row_of(j, q);
 #pragma unroll
                 for (int i = 0; i < 5; ++i) {
-                    const int gi = gs + i;
+                    const int gi = s_lo + 4 * run + i;
                     const float2 v = row[min(max(gi, 0), g.n_samp - 1)];
                     const bool ok = gi >= 0 && gi < g.n_samp;
                     x[i] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);
                 }
             }
-            // frames past the end read the last frame; their sums are never written
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                st[q][i] = make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
-        }
-        prx = rxd[(size_t)j * npix + pix];
-        pph = rxp[(size_t)j * npix + pix];
-    };
-    auto store = [&](int b, const float4 (&st)[NQ][4]) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int e = t + q * kDasThreads;
-            const int fl = das_frame<RUNS>(e), run = das_run<RUNS>(e);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) buf[b][fl][das_slot(fl, 4 * run + i)] = st[q][i];
+                buf[b][fl][das_slot(fl, 4 * run + i)] =
+                    make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
         }
     };
 
@@ -129,48 +134,61 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
         const float fl = floorf(s);
         const float fr = s - fl;
         const int idx = min(max((int)fl + sti_p - s_lo, 0), LEN - 1);
-        // four LDS reads in flight: frame f + 4 is requested while frame f is applied
-        float4 vq[4];
+        // kAhead LDS reads in flight: frame f + kAhead is requested while frame f
+        // is applied
+        constexpr int kAhead = 4;
+        float4 vq[kAhead];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) vq[f] = buf[cur][f][das_slot(f, idx)];
+        for (int f = 0; f < kAhead; ++f) vq[f] = buf[cur][f][das_slot(f, idx)];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-            const float4 v = vq[f & 3];
-            if (f + 4 < FB) vq[f & 3] = buf[cur][f + 4][das_slot(f + 4, idx)];
+            const float4 v = vq[f % kAhead];
+            if (f + kAhead < FB) vq[f % kAhead] = buf[cur][f + kAhead][das_slot(f + kAhead, idx)];
             const float xr = fmaf(fr, v.z, v.x);
             const float xi = fmaf(fr, v.w, v.y);
             acc[f].x = fmaf(cph.x, xr, fmaf(-cph.y, xi, acc[f].x));
             acc[f].y = fmaf(cph.x, xi, fmaf(cph.y, xr, acc[f].y));
         }
+        // the sums are complete here: the compiler may not sink this arithmetic
+        // past the store's branch (which would keep every LDS read live at once)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) asm volatile("" : "+v"(acc[f].x), "+v"(acc[f].y));
     };
 
     const int n = g.n_elem, last = n - 1;
-    load(0, sa, pa, qa);
-    store(0, sa);
-    float crx = pa;
-    float2 cph = qa;
+    load(0, sa);
+    store(0, 0, wj[0], sa);
+    // the receive delay and phasor of the element being applied, and of the next
+    float crx = rxd[pix], nrx;
+    float2 cph = rxp[pix], nph;
     int s_lo = wj[0];
-    load(min(1, last), sb, pb, qb);
+    load(min(1, last), sb);
     __syncthreads();
     // the last steps re-stage the last element into the idle buffer, so the
     // loop body has no branch around the stores
     for (int j = 0; j < n; j += 2) {
         // buf[0] holds element j, sb element j + 1
-        load(min(j + 2, last), sa, pa, qa);
+        int s_nx = wj[min(j + 1, last)];
+        load(min(j + 2, last), sa);
+        nrx = rxd[(size_t)min(j + 1, last) * npix + pix];
+        nph = rxp[(size_t)min(j + 1, last) * npix + pix];
         apply(0, crx, cph, s_lo);
-        store(1, sb);
-        crx = pb;
-        cph = qb;
-        s_lo = wj[min(j + 1, last)];
+        store(1, min(j + 1, last), s_nx, sb);
+        crx = nrx;
+        cph = nph;
+        s_lo = s_nx;
         __syncthreads();
         if (j + 1 < n) {
             // buf[1] holds element j + 1, sa element j + 2
-            load(min(j + 3, last), sb, pb, qb);
+            s_nx = wj[min(j + 2, last)];
+            load(min(j + 3, last), sb);
+            nrx = rxd[(size_t)min(j + 2, last) * npix + pix];
+            nph = rxp[(size_t)min(j + 2, last) * npix + pix];
             apply(1, crx, cph, s_lo);
-            store(0, sa);
-            crx = pa;
-            cph = qa;
-            s_lo = wj[min(j + 2, last)];
+            store(0, min(j + 2, last), s_nx, sa);
+            crx = nrx;
+            cph = nph;
+            s_lo = s_nx;
             __syncthreads();
         }
     }

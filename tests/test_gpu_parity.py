@@ -60,6 +60,27 @@ def test_beamform_parity(torch, ulm, case, tiny_cfg, tiny_iq):
             assert e <= BEAMFORM_TOL
 
 
+def test_beamform_record_edges(torch, ulm, tiny_cfg):
+    """Receive windows that cross both ends of the record.  On the tiny geometry
+    the echoes arrive 5.2-14.2 us after transmit (4-10 mm depth, 6.4 mm aperture);
+    a record from 7 us to 13.7 us misses the shallowest and the deepest, so the
+    staging of those windows must read zeros outside the record, as the oracle's
+    interpolation does."""
+    sq = tiny_cfg.seq
+    cfg = tiny_cfg.with_(seq=replace(sq, t_start=7.0e-6, n_samp=160))
+    iq = sim.simulate(cfg, make_medium(cfg, 5))
+    say(f"[beamform record edges] iq {iq.shape}")
+    ref = beamform.beamform_proj(iq, cfg)
+    ctx = ulm.Context(cfg)
+    proj = ulm.rca_beamform_proj(ctx, _to_dev(torch, iq, torch.complex64))
+    torch.cuda.synchronize()
+    got = proj.cpu().numpy()
+    for o in range(2):
+        e = rel_l2(got[o, 0], ref[o, 0])
+        say(f"  plane o={o} rel-L2 {e:.2e}")
+        assert e <= BEAMFORM_TOL
+
+
 def _filter_input(F, nz, nu, seed):
     st = np.stack([arrays.clutter_stack(nz * nu, F, rank=6, seed=seed + o) for o in range(2)])
     return st.reshape(2, 1, F, nz, nu)

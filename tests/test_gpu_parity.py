@@ -81,6 +81,26 @@ def test_beamform_record_edges(torch, ulm, tiny_cfg):
         assert e <= BEAMFORM_TOL
 
 
+def test_beamform_wide_window(torch, ulm, tiny_cfg):
+    """Sampled at 40 MHz, a tile of the tiny grid spans more than 64 and fewer than
+    128 samples (the span grows by about 2.2 samples per MHz there; 60 MHz gives
+    132 and is refused), so stage 1 stages 128-sample windows: two runs of four
+    samples per thread instead of one."""
+    pr, sq = tiny_cfg.probe, tiny_cfg.seq
+    cfg = tiny_cfg.with_(probe=replace(pr, fs=40e6), seq=replace(sq, n_samp=432))
+    iq = sim.simulate(cfg, make_medium(cfg, 6))
+    say(f"[beamform 40 MHz] iq {iq.shape}")
+    ref = beamform.beamform_proj(iq, cfg)
+    ctx = ulm.Context(cfg)
+    proj = ulm.rca_beamform_proj(ctx, _to_dev(torch, iq, torch.complex64))
+    torch.cuda.synchronize()
+    got = proj.cpu().numpy()
+    for o in range(2):
+        e = rel_l2(got[o, 0], ref[o, 0])
+        say(f"  plane o={o} rel-L2 {e:.2e}")
+        assert e <= BEAMFORM_TOL
+
+
 def _filter_input(F, nz, nu, seed):
     st = np.stack([arrays.clutter_stack(nz * nu, F, rank=6, seed=seed + o) for o in range(2)])
     return st.reshape(2, 1, F, nz, nu)

@@ -78,6 +78,7 @@ def _create(cfg_struct):
     (lambda c: setattr(c, "n_blocks", 0), "grid"),
     (lambda c: setattr(c, "nu", 4000), "NCC band"),
     (lambda c: setattr(c, "z0", -1e-3), "z0"),
+    (lambda c: setattr(c, "n_samp", 4), "n_samp"),
 ])
 def test_invalid_config_rejected_on_host(mutate, msg):
     from synth import cfg_paper

@@ -350,7 +350,7 @@ __global__ void cnn_d2s_kernel(const float *__restrict__ logits, float *__restri
 // in fine raster order and not below the later ones.  Records are compacted in
 // (coarse column, fine row, fine column) order into the row's staging slot.
 template <typename T>
-__global__ __launch_bounds__(256) void cnn_head_decode_kernel(
+__global__ __launch_bounds__(256, 4) void cnn_head_decode_kernel(
     const T *__restrict__ a6, const float *__restrict__ p, const float2 *__restrict__ P, float thr,
     int H, int W, int n0, int F, ulm_loc_t *__restrict__ staged, int *__restrict__ row_cnt,
     int row_cap, int *__restrict__ status)

@@ -220,3 +220,113 @@ def test_beamform_linear_and_mirror():
     assert np.max(np.abs(pa[1] - pb[0])) <= 1e-11 * scale
     pab = beamform.beamform_proj(a + 2.5j * b, cfg)
     assert np.max(np.abs(pab - (pa + 2.5j * pb))) <= 1e-11 * scale
+
+
+STEERED_DEG = (-8.0, -6.0, -2.0, 2.0, 6.0, 8.0)
+
+
+def _steered_closed_form_error(cfg, iu, iz):
+    """|S - closed form| / |closed form| at the scatterer's pixel, and whether |S|
+    peaks there, for one noise-free scatterer in the reference slice (v = v_ref).
+
+    The expected value uses the geometric time of flight (wavefront through the
+    first-firing array edge plus point-to-line distance), not the oracle's delay
+    formula: A e^{-i 4 pi f0 z / c} sum_e [(1 - fr_e) G(fr_e) + fr_e G(1 - fr_e)],
+    where fr_e is the fractional IQ sample index of that time of flight."""
+    p = _pixel_centre_point(cfg, iu, iz, v=cfg.grid.v_ref)
+    iq = sim.simulate(cfg, point_medium(cfg, [p]), with_noise=False)
+    plane = beamform.stage1_slices(iq, cfg)[0, 0, 0]
+    tof = _geometric_delays(cfg, p, 0, 0)
+    s = (tof - cfg.seq.t_start) * cfg.probe.fs
+    fr = s - np.floor(s)
+    sig = sim.pulse_sigma(cfg) * cfg.probe.fs
+    G = lambda x: np.exp(-x * x / (2 * sig * sig))
+    expect = np.exp(-4j * np.pi * cfg.probe.f0 * p[2] / cfg.probe.c) * \
+        np.sum((1 - fr) * G(fr) + fr * G(1 - fr))
+    peak = np.unravel_index(np.argmax(np.abs(plane)), plane.shape) == (iz, iu)
+    return abs(plane[iz, iu] - expect) / abs(expect), peak
+
+
+@pytest.mark.parametrize("deg", STEERED_DEG)
+def test_stage1_single_scatterer_closed_form_steered(deg):
+    """Section II-A1, stage 1 with a steered plane wave: a scatterer at a pixel
+    centre of the reference slice gives the closed-form value at that pixel (the
+    steered transmit delay z cos(theta) + v sin(theta) + (L/2)|sin(theta)| enters
+    only through the geometric time of flight), and |S| peaks at that pixel."""
+    cfg = with_angles(with_frames(cfg_tiny(), 1), [deg])
+    for iu, iz in ((21, 37), (45, 12)):
+        err, peak = _steered_closed_form_error(cfg, iu, iz)
+        assert err <= 1e-9, (deg, iu, iz, err)
+        assert peak, (deg, iu, iz)
+
+
+def _coherent_slab(cfg):
+    """Four slices centred on the reference slice: a slab thin enough that a steered
+    transmit's phase turns by well under a quarter cycle across it."""
+    g = cfg.grid
+    return cfg.with_(grid=replace(g, nv=4, v0=g.v_ref - 1.5 * g.dv, n_blocks=1))
+
+
+POINT_TARGETS = ((16, 14), (44, 20), (24, 42), (48, 50), (32, 30))   # (iu, iz), 14+ px apart
+
+
+def _point_target_errors(cfg):
+    """Section II-A4 end to end on isolated point targets at pixel centres of the
+    reference slice: simulate, beamform (both stages, coherent slab), filter with
+    cutoff 0 (the identity), NCC-localise.  Returns the distance in pixels from
+    each target to the nearest detection, for the x-z plane (targets at y = 0)
+    and for the y-z plane (the mirrored medium)."""
+    from oracle import clutter, localize
+    g = cfg.grid
+    pts = np.array([(g.u0 + iu * g.du, g.v_ref, g.z0 + iz * g.dz) for iu, iz in POINT_TARGETS])
+    out = []
+    for plane, pos in ((0, pts), (1, pts[:, [1, 0, 2]])):
+        iq = sim.simulate(cfg, point_medium(cfg, pos), with_noise=False)
+        P = beamform.beamform_proj(iq, cfg)
+        Pf, _ = clutter.filter_planes(P, 0)
+        assert np.array_equal(Pf, P)
+        recs, _, _ = localize.localize(Pf, cfg)
+        r = recs[recs["plane"] == plane]
+        for iu, iz in POINT_TARGETS:
+            out.append(float(np.min(np.hypot(r["u"] - iu, r["z"] - iz))))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("deg", STEERED_DEG)
+def test_point_targets_end_to_end(deg):
+    """Isolated point targets through simulation -> two-stage beamforming ->
+    identity filter -> NCC come back within 0.05 px of their known positions at
+    every steering angle, one angle at a time.  The targets sit at pixel centres
+    of the slab's middle, where the projected PSF is symmetric about the target,
+    so any delay error shows as a displacement."""
+    cfg = with_angles(_coherent_slab(with_frames(cfg_tiny(), 1)), [deg])
+    err = _point_target_errors(cfg)
+    assert err.max() <= 0.05, (deg, err)
+
+
+def _planted_das(monkeypatch, tmp_path, old, new):
+    """Load a copy of the oracle's DAS loops with one planted mistake."""
+    from oracle import _clib
+    src = open(os.path.join(os.path.dirname(beamform.__file__), "das.c")).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "das_planted.c"
+    path.write_text(src.replace(old, new))
+    h = _clib.load(_clib.compile_c(str(path), str(tmp_path / "libdas_planted.so")))
+    monkeypatch.setattr(_clib, "_handle", h)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("+ 0.5 * L * fabs(sin(theta))", ""),          # firing offset of a steered plane wave dropped
+    ("z * cos(theta)", "z"),                         # wavefront depth term without cos(theta)
+])
+def test_steered_delay_planted_mistakes(monkeypatch, tmp_path, old, new):
+    """Planted mistakes in the oracle's steered transmit delay break the steered
+    closed form at every nonzero angle and the point-target pin at 6 and 8 deg."""
+    _planted_das(monkeypatch, tmp_path, old, new)
+    for deg in STEERED_DEG:
+        cfg = with_angles(with_frames(cfg_tiny(), 1), [deg])
+        err, _ = _steered_closed_form_error(cfg, 21, 37)
+        assert err > 1e-3, (deg, err)
+    for deg in (6.0, 8.0):
+        cfg = with_angles(_coherent_slab(with_frames(cfg_tiny(), 1)), [deg])
+        assert _point_target_errors(cfg).max() > 0.1, deg

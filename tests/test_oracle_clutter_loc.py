@@ -171,10 +171,10 @@ def test_spot_at_pixel_centre_and_mirror():
 
 
 def test_thresholds_and_tie_break():
-    """A plateau of two equal NCC maxima yields exactly one detection (the later
-    one in raster order: a pixel must exceed earlier neighbours and only match
-    later ones); weak spots below
-    alpha * max are rejected."""
+    """A plateau of two equal NCC maxima yields exactly one detection, the earlier
+    one in raster order: a pixel must exceed its earlier neighbours and only match
+    its later ones, so the later pixel of the pair fails against the earlier one.
+    Weak spots below alpha * max are rejected."""
     N = np.zeros((7, 7))
     N[3, 2] = N[3, 3] = 0.9
     I = np.ones((7, 7))
@@ -199,3 +199,55 @@ def test_ssim_identity_and_range():
     a = rng.uniform(0, 1, (40, 40))
     assert abs(pipeline.ssim(a, a) - 1.0) < 1e-12
     assert pipeline.ssim(a, rng.uniform(0, 1, (40, 40))) < 0.2
+
+
+def test_ssim_constant_images_closed_form():
+    """Constant images p and q have zero local variance, so SSIM reduces to its
+    luminance term (2pq + C1)/(p^2 + q^2 + C1) with C1 = (0.01 R)^2 (Wang et al.
+    2004): 0.3001/0.3401 for p = 0.3, q = 0.5, R = 1, at every pixel."""
+    a = np.full((23, 31), 0.3)
+    b = np.full((23, 31), 0.5)
+    assert abs(pipeline.ssim(a, b, data_range=1.0) - 0.3001 / 0.3401) < 1e-13
+    assert abs(pipeline.ssim(a, a, data_range=1.0) - 1.0) < 1e-13
+
+
+def test_ssim_brute_force_windows():
+    """SSIM equals the mean over pixels of the index computed from explicit
+    Gaussian-weighted local statistics (sigma 1.5, radius 5, mirror boundary
+    without repeating the edge sample), summed pixel by pixel; and it is
+    symmetric and invariant under a joint transpose."""
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0, 1, (14, 17))
+    b = 0.6 * a + 0.4 * rng.uniform(0, 1, (14, 17))
+    R = 1.0
+    x = np.arange(-5, 6)
+    w = np.exp(-x * x / (2 * 1.5 ** 2))
+    w2 = np.outer(w, w) / w.sum() ** 2
+
+    def mirror(i, n):
+        while i < 0 or i >= n:
+            i = -i if i < 0 else 2 * (n - 1) - i
+        return i
+
+    vals = []
+    for i in range(a.shape[0]):
+        for j in range(a.shape[1]):
+            s = {"a": 0.0, "b": 0.0, "aa": 0.0, "bb": 0.0, "ab": 0.0}
+            for di in range(-5, 6):
+                for dj in range(-5, 6):
+                    ii, jj = mirror(i + di, a.shape[0]), mirror(j + dj, a.shape[1])
+                    wt = w2[di + 5, dj + 5]
+                    s["a"] += wt * a[ii, jj]
+                    s["b"] += wt * b[ii, jj]
+                    s["aa"] += wt * a[ii, jj] ** 2
+                    s["bb"] += wt * b[ii, jj] ** 2
+                    s["ab"] += wt * a[ii, jj] * b[ii, jj]
+            va, vb = s["aa"] - s["a"] ** 2, s["bb"] - s["b"] ** 2
+            cab = s["ab"] - s["a"] * s["b"]
+            c1, c2 = (0.01 * R) ** 2, (0.03 * R) ** 2
+            vals.append((2 * s["a"] * s["b"] + c1) * (2 * cab + c2) /
+                        ((s["a"] ** 2 + s["b"] ** 2 + c1) * (va + vb + c2)))
+    got = pipeline.ssim(a, b, data_range=R)
+    assert abs(got - np.mean(vals)) < 1e-12
+    assert abs(pipeline.ssim(b, a, data_range=R) - got) < 1e-13
+    assert abs(pipeline.ssim(a.T, b.T, data_range=R) - got) < 1e-13

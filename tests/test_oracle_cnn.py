@@ -84,3 +84,28 @@ def test_adam_matches_closed_form_first_step():
     g = {"a": np.array([0.5, -4.0, 1e-3])}
     cnn.adam_step(p, g, {}, lr=0.01, eps=0.0)
     assert np.allclose(p["a"], [0.99, -1.99, 2.99])
+
+
+def test_adam_bias_correction_later_steps():
+    """Adam's bias correction at t = 2 and 3, from hand-derived closed forms.
+
+    Constant gradient g (eps = 0): m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so
+    the corrected moments are g and g^2 and every step moves a weight by exactly
+    lr sign(g).  Gradient +1 then -1: the corrected first moment at t = 2 is
+    -(1 - b1)/(1 + b1) = -1/19 and the corrected second moment is 1, so the
+    second step moves the weight by +lr/19.  Without the bias correction the
+    second step would be (1 - b1^2)/sqrt(1 - b2^2) = 4.25 times larger."""
+    lr = 0.01
+    p = {"a": np.array([1.0, -2.0, 3.0])}
+    g = {"a": np.array([0.5, -4.0, 1e-3])}
+    st = {}
+    for t in range(1, 4):
+        cnn.adam_step(p, g, st, lr=lr, eps=0.0)
+        assert np.allclose(p["a"], np.array([1.0, -2.0, 3.0]) - t * lr * np.sign(g["a"]),
+                           rtol=0, atol=1e-14), t
+    q = {"w": np.array([0.0])}
+    st = {}
+    cnn.adam_step(q, {"w": np.array([1.0])}, st, lr=lr, eps=0.0)
+    assert abs(q["w"][0] + lr) < 1e-15
+    cnn.adam_step(q, {"w": np.array([-1.0])}, st, lr=lr, eps=0.0)
+    assert abs(q["w"][0] - (-lr + lr / 19.0)) < 1e-15

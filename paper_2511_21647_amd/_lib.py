@@ -6,9 +6,11 @@ fallback: if the library is not built, importing this module raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -181,6 +183,24 @@ def _stream(stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+# Contexts still open when the interpreter exits are closed by an exit hook,
+# while the HIP runtime (and any profiler attached to it) is still up, instead
+# of by object finalisation during interpreter teardown.
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    live = list(_LIVE_CONTEXTS)
+    if not live:
+        return
+    torch = _torch()
+    if torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+    for c in live:
+        c.close()
+
+
 class Context:
     """A library context plus its device workspace (a torch uint8 tensor)."""
 
@@ -200,6 +220,7 @@ class Context:
         self.ws = torch.zeros(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
         self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        _LIVE_CONTEXTS.add(self)
 
     @property
     def proj_shape(self):
@@ -212,9 +233,12 @@ class Context:
         return (c.n_frames, 2, c.n_angles, c.n_elem, c.n_samp)
 
     def close(self):
+        """Destroys the library context (tables, events) and drops the workspace.
+        The caller synchronises work that still uses them first."""
         if getattr(self, "handle", None):
             _lib.ulm_destroy(self.handle)
             self.handle = None
+            self.ws = None
 
     def __del__(self):
         try:

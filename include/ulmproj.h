@@ -251,6 +251,32 @@ int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *co
                         int32_t capacity, ulm_loc3d_t *out, int32_t out_capacity,
                         int32_t *out_count, void *pws, size_t pws_bytes, void *stream);
 
+/* Size of the library-owned device scratch array used by
+ * ulm_pair_planes_noalloc (one array per device). */
+#define ULM_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * ulm_pair_planes without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * ulm_pair_planes minus `pws`: the workspace lives in a fixed library-owned
+ * device array of ULM_NOALLOC_SCRATCH_BYTES per device, whose address
+ * ulm_create looks up (once per device).  The call allocates nothing.
+ *   Limit: ulm_pair_workspace_size(ctx, capacity) must not exceed
+ *   ULM_NOALLOC_SCRATCH_BYTES (about 8 M input records at 300 frames);
+ *   larger `capacity` returns INVALID_ARG before anything is launched.
+ *   Every call on one device shares that device's array: calls that overlap
+ *   in time on one device (other streams, other contexts or threads) race and
+ *   must be serialised by the caller.  The array keeps the last call's
+ *   contents; the pairing overwrites every word it reads, so nothing needs
+ *   clearing between calls.
+ * Errors: INVALID_ARG, HIP (also if the array's address could not be looked
+ * up on ctx's device).
+ */
+int32_t ulm_pair_planes_noalloc(ulm_ctx_t *ctx, const ulm_loc_t *locs, const int32_t *count,
+                                int32_t capacity, ulm_loc3d_t *out, int32_t out_capacity,
+                                int32_t *out_count, void *stream);
+
 /* Byte offset of the stage-1 reference slices S[2][K][F][Nz][Nu] (c64) inside
  * the workspace, where rca_beamform_stage1 leaves them. */
 int32_t ulm_slices_offset(const ulm_ctx_t *ctx, size_t *offset);

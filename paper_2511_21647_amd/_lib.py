@@ -43,7 +43,7 @@ EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
            "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
            "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
            "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize",
-           "ulm_pair_workspace_size", "ulm_pair_planes", "ulm_slices_offset",
+           "ulm_pair_workspace_size", "ulm_pair_planes", "ulm_pair_planes_noalloc", "ulm_slices_offset",
            "ulm_motion_workspace_size", "ulm_motion_estimate", "ulm_separate")
 
 
@@ -123,6 +123,7 @@ def _load():
                               vp], i32),
         "ulm_pair_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
         "ulm_pair_planes": ([vp, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
+        "ulm_pair_planes_noalloc": ([vp, vp, vp, i32, vp, i32, vp, vp], i32),
         "ulm_slices_offset": ([vp, ctypes.POINTER(sz)], i32),
         "ulm_motion_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
         "ulm_motion_estimate": ([vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
@@ -582,6 +583,24 @@ def ulm_pair_planes(ctx: Context, locs, count, capacity: int, out_capacity: int,
     _check(_lib.ulm_pair_planes(ctx.handle, _ptr(locs), _ptr(count), int(capacity), _ptr(out),
                                 int(out_capacity), _ptr(out_count), ws.ptr, ws.nbytes,
                                 _stream(stream)))
+    return out, out_count
+
+
+ULM_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def ulm_pair_planes_noalloc(ctx: Context, locs, count, capacity: int, out_capacity: int, out,
+                            out_count, stream=None):
+    """ulm_pair_planes with the library's own scratch array instead of a
+    workspace; the caller passes preallocated `out` and `out_count`."""
+    torch = _torch()
+    _require_rows(locs, capacity, "locs")
+    _require(count, torch.int32, (1,), "count")
+    _require_rows(out, out_capacity, "out")
+    _require(out_count, torch.int32, (1,), "out_count")
+    _check(_lib.ulm_pair_planes_noalloc(ctx.handle, _ptr(locs), _ptr(count), int(capacity),
+                                        _ptr(out), int(out_capacity), _ptr(out_count),
+                                        _stream(stream)))
     return out, out_count
 
 

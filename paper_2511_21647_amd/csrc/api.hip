@@ -41,6 +41,8 @@ std::vector<float2> separate_twiddles(int F);
 hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, float2 *out,
                            hipStream_t st);
 size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
+hipError_t scratch_init(int device);
+void *scratch_ptr(int device);
 hipError_t cnn_images(const float2 *P, const float *fmax, float *x0, int npix, int n0, int nb,
                       hipStream_t st);
 hipError_t cnn_forward_heat(const float *params, const float *x0, float *heat, int B, int H, int W,
@@ -319,6 +321,8 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
     };
     hipError_t e;
     if ((e = hipGetDevice(&ctx->device)) != hipSuccess) return cleanup(e, "hipGetDevice");
+    // device address of the library-owned scratch array (ulm_pair_planes_noalloc)
+    if ((e = scratch_init(ctx->device)) != hipSuccess) return cleanup(e, "hipGetSymbolAddress(scratch)");
     if ((e = hipMalloc(&ctx->tab.stx, sizeof(float) * stx.size())) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->tab.phz, sizeof(float2) * phz.size())) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->tab.taps, sizeof(float2) * taps.size())) != hipSuccess) return cleanup(e, "hipMalloc");
@@ -660,6 +664,28 @@ extern "C" int32_t ulm_pair_planes(ulm_ctx_t *ctx, const ulm_loc_t *locs, const 
     HIP_TRY(launch_pairing(ctx, locs, count, capacity, out, out_capacity, out_count, (char *)pws,
                            (hipStream_t)stream),
             "ulm_pair_planes");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_pair_planes_noalloc(ulm_ctx_t *ctx, const ulm_loc_t *locs,
+                                           const int32_t *count, int32_t capacity,
+                                           ulm_loc3d_t *out, int32_t out_capacity,
+                                           int32_t *out_count, void *stream) {
+    if (!ctx || !count || !out_count || capacity < 0 || out_capacity < 0 ||
+        (capacity > 0 && !locs) || (out_capacity > 0 && !out))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    const size_t need = pair_workspace_bytes(ctx->geo.n_planes, ctx->geo.n_frames, std::max(capacity, 1));
+    if (need > (size_t)ULM_NOALLOC_SCRATCH_BYTES)
+        return fail(ULM_ERR_INVALID_ARG,
+                    "capacity too large for the library scratch array: the pairing needs " +
+                        std::to_string(need) + " bytes, the array holds " +
+                        std::to_string((size_t)ULM_NOALLOC_SCRATCH_BYTES));
+    if (((uintptr_t)locs & 15) != 0) return fail(ULM_ERR_INVALID_ARG, "localisation list not 16-byte aligned");
+    char *pws = (char *)scratch_ptr(ctx->device);
+    if (!pws) return fail(ULM_ERR_HIP, "library scratch array has no device address on this device");
+    HIP_TRY(launch_pairing(ctx, locs, count, capacity, out, out_capacity, out_count, pws,
+                           (hipStream_t)stream),
+            "ulm_pair_planes_noalloc");
     return ULM_OK;
 }
 

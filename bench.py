@@ -10,6 +10,9 @@ is already resident in HBM: stage-1 DAS -> stage-2 projection -> clutter filter
   bf16_cnn  BF16 hi/lo split Gram and removal with FP32 accumulation, FP64
             eigen; the learned CNN localiser (BF16 activations) with the
             trained weights in paper_2511_21647_amd/weights/
+  xdoppler  the plain path with XDoppler before the NCC: cross projections of
+            the other orientation's volume, both stacks filtered, 3-frame
+            cross-correlation of the filtered stacks
   slab_p8   the paper's sub-block projection: slabs of 8 slices (2 x 35
             planes), plain filter and NCC on every slab plane, then the
             XZ/YZ pairing into 3D localisations
@@ -107,6 +110,9 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     if form == "bf16_cnn":
         cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(ctx, 64), "cuda")
     pair = form == "slab_p8"
+    xd = form == "xdoppler"
+    if xd:
+        cross = torch.empty(ctx.proj_shape, dtype=torch.complex64, device="cuda")
     if pair:
         pair_cap = 1 << 24
         pairs = torch.empty((pair_cap, 8), dtype=torch.int32, device="cuda")
@@ -118,8 +124,13 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
         ulm.rca_beamform_stage1(ctx, iq)
         if ev: ev[1].record()
         ulm.rca_beamform_stage2(ctx, proj)
+        if xd:
+            ulm.rca_beamform_cross(ctx, cross)
         if ev: ev[2].record()
         ulm.svd_clutter_filter(ctx, proj, eig)
+        if xd:
+            ulm.svd_clutter_filter(ctx, cross, eig)
+            ulm.ulm_xdoppler(ctx, proj, cross, 3, out=proj)
         if ev: ev[3].record()
         if form == "bf16_cnn":
             ulm.ulm_cnn_localize(ctx, cnn_params, proj, cap, ulm.CNN_THRESHOLD, 64, ulm.ULM_CNN_BF16, locs,
@@ -144,7 +155,8 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
     t1 = time.perf_counter()
     ulm.ulm_check_status(ctx, count, cap)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    names = ["das_stage1", "stage2_projection", "clutter_filter",
+    names = ["das_stage1", "stage2_projection" + ("_and_cross" if xd else ""),
+             "clutter_filter" + ("_both_and_xdoppler" if xd else ""),
              "cnn_localize" if form == "bf16_cnn" else "ncc_localize"] + (["pairing_3d"] if pair else [])
     stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps
              for i, n in enumerate(names)}
@@ -154,6 +166,8 @@ def run_form(form, cfg, ctx, iq, args, cnn_params=None):
         n_det = (n_det, int(pair_count.item()))
         del pairs, pws
     del proj, eig, locs, cws
+    if xd:
+        del cross
     torch.cuda.empty_cache()
     return ms_step, stage, n_det
 
@@ -301,6 +315,14 @@ def run_gpu(args):
     log(f"motion estimation: {forms['plain']['motion_estimation']}")
     forms["plain"]["mb_separation"] = time_separation(cfg, ctx, args)
     log(f"MB separation: {forms['plain']['mb_separation']}")
+    if args.form == "both":
+        # XDoppler: the other orientation's volume projected onto every plane,
+        # both stacks filtered, 3-frame cross-correlation, NCC on its image
+        ms_x, stage_x, n_x = run_form("xdoppler", cfg, ctx, iq, args)
+        forms["xdoppler"] = {"ms_per_ensemble": round(ms_x, 3),
+                             "stages_ms": {k: round(v, 3) for k, v in stage_x.items()},
+                             "detections": n_x, "window": 3}
+        log(f"xdoppler: {ms_x:.2f} ms/ensemble {stage_x}")
     if args.form == "both" and os.path.exists(WEIGHTS):
         ctx_b = ulm.Context(cfg, precision=ulm.ULM_PREC_BF16X3)
         params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()
@@ -524,6 +546,77 @@ def profile_das(args):
     log("profile run done: one das_stage1_kernel launch and one 1 GiB copy")
 
 
+def profile_kernels(args):
+    """One launch each of the clutter filter's Gram in both precision forms and
+    of the CNN localiser on the paper-scale ensemble (for rocprofv3 --pmc runs
+    of the matrix-core counters)."""
+    import numpy as np
+    import torch
+    import paper_2511_21647_amd as ulm
+    cfg, ctx, iq = setup("fp64gram")
+    proj = ulm.rca_beamform_proj(ctx, iq)
+    del iq
+    ctx_b = ulm.Context(cfg, precision=ulm.ULM_PREC_BF16X3)
+    d = proj.clone()
+    ulm.svd_clutter_filter(ctx, proj)
+    ulm.svd_clutter_filter(ctx_b, d)
+    params = torch.from_numpy(np.load(WEIGHTS).astype(np.float32)).cuda()
+    cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(ctx_b, 64), "cuda")
+    cap = 4_000_000
+    locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ulm.ulm_cnn_localize(ctx_b, params, d, cap, ulm.CNN_THRESHOLD, 64, ulm.ULM_CNN_BF16, locs, count,
+                         ws=cws)
+    torch.cuda.synchronize()
+    ctx_b.close()
+    ctx.close()
+    log("profile run done: both Gram forms, the CNN localiser")
+
+
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F64", "MfmaUtil")
+
+
+def summarize_mfma(d, out_md, cmd):
+    """Matrix-core counters per kernel (summed over its dispatches) from a
+    rocprofv3 --pmc run of --profile-kernels: MfmaUtil (rocprofiler's derived
+    counter: MFMA-busy cycles over GUI-active cycles x SIMDs) and the issued
+    MFMA flop (MOPS x 512)."""
+    per = {}
+    for r in _read_counter_rows(d):
+        name = r.get("Kernel_Name", "")
+        if not name or "ulm" not in name:
+            continue
+        key = (r.get("Dispatch_Id"), name)
+        per.setdefault(key, {})[r["Counter_Name"]] = per.get(key, {}).get(r["Counter_Name"], 0.0) \
+            + float(r["Counter_Value"])
+    agg = {}
+    for (_, name), vals in per.items():
+        short = readable(name).split("(")[0].replace("void ", "")
+        a = agg.setdefault(short, {"dispatches": 0, "util": []})
+        a["dispatches"] += 1
+        for k, v in vals.items():
+            if k == "MfmaUtil":
+                a["util"].append(v)
+            else:
+                a[k] = a.get(k, 0.0) + v
+    lines = ["| Kernel | Dispatches | MfmaUtil (%) per dispatch, mean | MFMA-busy cycles (sum) | "
+             "BF16 MFMA flop issued | FP64 MFMA flop issued |", "|---|---|---|---|---|---|"]
+    for short, a in sorted(agg.items(), key=lambda kv: -kv[1].get("SQ_VALU_MFMA_BUSY_CYCLES", 0)):
+        if a.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) <= 0:
+            continue
+        util = sum(a["util"]) / len(a["util"]) if a["util"] else float("nan")
+        lines.append(f"| `{short}` | {a['dispatches']} | {util:.1f} | "
+                     f"{a.get('SQ_VALU_MFMA_BUSY_CYCLES', 0):.3g} | "
+                     f"{512 * a.get('SQ_INSTS_VALU_MFMA_MOPS_BF16', 0):.3g} | "
+                     f"{512 * a.get('SQ_INSTS_VALU_MFMA_MOPS_F64', 0):.3g} |")
+    text = (f"Command (run from the repository root on one MI355X):\n\n```\n{cmd}\n```\n\n"
+            + "\n".join(lines) + "\n")
+    with open(out_md, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
 def _read_counter_rows(d):
     rows = []
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
@@ -569,6 +662,118 @@ def summarize_pmc(d_fetch, d_write):
     print(json.dumps(rec))
 
 
+# Algorithmic work per launch for the kernel-trace summary, on the paper-scale
+# workload (F frames, NPIX pixels per plane, K transmits per orientation, NC
+# elements).  `planes` / `images` are read off the launch grid.
+F_P, NPIX_P, K_P, NC_P, C_P = 300, 250 * 274, 9, 128, 20
+GRAM_WGS_PER_PLANE = 15 * 34           # 64x64 block pairs x 2048-pixel chunks
+BF16_PEAK_TFLOPS = 2500.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _kernel_work(name, wgs, gy, gz):
+    """(bound, work per launch, unit of work, peak, note) or None."""
+    plane_bytes = F_P * NPIX_P * 8
+    short = name.split("(")[0].replace("void ", "")
+    if "das_stage1_kernel" in short:
+        return ("alu", DAS_FLOPS_PER_EVAL * 2 * K_P * F_P * NPIX_P * NC_P, "flop",
+                FP32_VECTOR_PEAK_TFLOPS, "12 flop per channel-pixel-transmit-frame evaluation")
+    if "gram_f64_kernel" in short or "gram_bf16x3_kernel" in short:
+        planes = max(1, round(wgs / GRAM_WGS_PER_PLANE))
+        flops = planes * 4.0 * F_P * F_P * NPIX_P        # Hermitian half, 8 flop per complex MAC
+        if "f64" in short:
+            return ("mfma", flops, "flop", FP64_PEAK_TFLOPS, f"{planes} planes, FP64 MFMA")
+        return ("mfma", flops, "flop", BF16_PEAK_TFLOPS,
+                f"{planes} planes; the split form issues 6 BF16 products per real product")
+    if "removal" in short and "tables" not in short:
+        planes = gy
+        return ("hbm", 2 * planes * plane_bytes, "byte", HBM_PEAK_GBS / 1e3,
+                f"{planes} planes read and written once")
+    if "stage2_fir_kernel" in short:
+        planes = 2 * (35 if "<4>" in short else 1)
+        return ("hbm", 2 * K_P * F_P * NPIX_P * 8 + planes * plane_bytes, "byte",
+                HBM_PEAK_GBS / 1e3, f"slices read once, {planes} planes written")
+    if "frame_max_kernel" in short or "ncc_band_kernel" in short:
+        planes = gz if "ncc_band" in short else max(1, round(wgs / F_P))    # one work-group per image
+        return ("hbm", planes * plane_bytes, "byte", HBM_PEAK_GBS / 1e3, f"{planes} planes read once")
+    if "cnn_conv_kernel" in short:
+        # the launch grid is the same for every batch; the median launch is a
+        # full batch of 64 images (600 = 9 x 64 + 24)
+        return ("mfma", 64 * NPIX_P * 32 * 288 * 2.0, "flop", BF16_PEAK_TFLOPS,
+                "one 32 -> 32 conv3x3 layer on 64 images, BF16 MFMA")
+    if "cross_profile_kernel" in short:
+        return ("hbm", 2 * K_P * F_P * NPIX_P * 8, "byte", HBM_PEAK_GBS / 1e3, "slices read once")
+    if "cross_project_kernel" in short:
+        return ("hbm", 2 * plane_bytes, "byte", HBM_PEAK_GBS / 1e3, "2 planes written")
+    if "xdoppler_kernel" in short:
+        return ("hbm", 3 * 2 * plane_bytes, "byte", HBM_PEAK_GBS / 1e3, "2 x 2 planes read, 2 written")
+    if "sep_kernel" in short:
+        return ("hbm", 7 * 2 * plane_bytes, "byte", HBM_PEAK_GBS / 1e3, "2 planes read, 6 x 2 written")
+    if "mot_corr_kernel" in short:
+        return ("mfma", 2.0 * 2 * K_P * F_P * 289 * NPIX_P, "flop", FP32_MFMA_PEAK_TFLOPS,
+                "2 flop per pixel, lag, frame, slice (289 lags)")
+    if "cnn_head_decode_kernel" in short:
+        images = gy
+        return ("hbm", images * NPIX_P * 32 * 2, "byte", HBM_PEAK_GBS / 1e3,
+                f"{images} images of BF16 activations read once")
+    return None
+
+
+def readable(name):
+    """Kernel name as printed, the mangled names of the templated CNN kernels
+    shown as ulm::<name><element type>."""
+    import re
+    m = re.match(r"_ZN3ulm(\d+)(\w+)", name)
+    if not m:
+        return name
+    base = m.group(2)[:int(m.group(1))]
+    return f"ulm::{base}<{'bf16' if 'DF16b' in name else 'float'}>"
+
+
+def summarize_trace(src, out_md, cmd):
+    """Per-kernel launch statistics of a rocprofv3 kernel trace (a rocpd SQLite
+    database or a kernel_trace.csv), grouped by kernel and launch grid, with the
+    roofline fraction of every kernel whose algorithmic work is known."""
+    import statistics
+    groups = {}
+    if src.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(src)
+        q = ("select name, grid_x / workgroup_x, grid_y, grid_z, duration from kernels")
+        for name, wgs, gy, gz, dur in con.execute(q):
+            groups.setdefault((name, int(wgs), int(gy), int(gz)), []).append(dur / 1e3)
+    else:
+        with open(src) as fh:
+            for r in csv.DictReader(fh):
+                wgs = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+                key = (r["Kernel_Name"], wgs, int(r["Grid_Size_Y"]), int(r["Grid_Size_Z"]))
+                groups.setdefault(key, []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    rows = [((readable(k[0]),) + k[1:], d) for k, d in rows]
+    lines = ["| Kernel | Work-groups | Calls | Mean (us) | Median (us) | Min (us) | Roofline |",
+             "|---|---|---|---|---|---|---|"]
+    for (name, wgs, gy, gz), d in rows:
+        if sum(d) < 50.0:
+            continue
+        short = name.split("(")[0].replace("void ", "")
+        mean, med = statistics.mean(d), statistics.median(d)
+        work = _kernel_work(name, wgs, gy, gz)
+        roof = ""
+        if work:
+            bound, w, unit, peak, note = work
+            rate = w / (med * 1e-6) / 1e12            # T(flop|byte)/s at the median launch
+            roof = (f"{bound}: {w:.3g} {unit} / launch, {rate:.3g} T{unit}/s of {peak:g}, "
+                    f"**{rate / peak:.1%}** ({note})")
+        lines.append(f"| `{short}` | {wgs * gy * gz} | {len(d)} | {mean:.1f} | {med:.1f} | "
+                     f"{min(d):.1f} | {roof} |")
+    text = (f"Command (run from the repository root on one MI355X):\n\n```\n{cmd}\n```\n\n"
+            + "\n".join(lines) + "\n")
+    with open(out_md, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,7 +783,14 @@ def main():
                     help="time the plain path only, or also the BF16 + CNN and slab forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-das", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="one launch each of both Gram forms and the CNN localiser "
+                         "(for rocprofv3 --pmc matrix-core counters)")
+    ap.add_argument("--summarize-mfma", nargs=3, metavar=("PMC_DIR", "OUT_MD", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE", "OUT_MD", "COMMAND"),
+                    help="write a per-kernel summary (with rooflines) of a rocprofv3 kernel "
+                         "trace (rocpd .db or kernel_trace.csv)")
     ap.add_argument("--stream", type=int, default=0, metavar="N")
     ap.add_argument("--inflight", type=int, default=1, metavar="N",
                     help="also time the plain path with N > 1 ensembles in flight on N streams "
@@ -588,6 +800,12 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this path runs on one GPU; multi-GPU runs are not supported "
@@ -595,6 +813,9 @@ def main():
         sys.exit(2)
     if args.profile_das:
         profile_das(args)
+        return
+    if args.profile_kernels:
+        profile_kernels(args)
         return
     if args.stream:
         run_stream(args)

@@ -55,7 +55,10 @@ extern "C" {
 
 /* precision of the Casorati Gram and the clutter removal */
 #define ULM_PREC_FP64GRAM 0   /* plain path: FP32 data, Gram and removal accumulated in FP64 */
-#define ULM_PREC_BF16X3   1   /* BF16 hi/lo split products on MFMA, FP32 accumulation       */
+#define ULM_PREC_BF16X3   1   /* Gram and removal on BF16 MFMA: every operand split into three
+                                 BF16 terms (hi, mid, lo), the six products of term orders
+                                 below three accumulated in FP32 per 16-pixel (Gram) or
+                                 8-frame (removal) K-step, those sums added in FP64        */
 
 typedef struct ulm_config {
     /* probe: n_elem row elements and n_elem column elements */
@@ -152,11 +155,50 @@ int32_t rca_beamform_stage1(ulm_ctx_t *ctx, const float *iq, void *ws, size_t ws
 int32_t rca_beamform_stage2(ulm_ctx_t *ctx, float *proj, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Cross projections for XDoppler (Section II-A4: beamforming and filtering run
+ * on the RC and CR volumes separately, and the filtered RC and CR stacks are
+ * cross-correlated before localisation).  Both orientations' volumes share one
+ * voxel grid, so plane (o, b) also receives the OTHER orientation o' = 1 - o's
+ * compounded volume, sum-projected over slab b onto plane o:
+ *   Q_{o,b}(v_i, z) = sum_k sum_{u in block b} S^{o'}_k^lin(u, z + (v_i - v_ref) t_k)
+ *                     * exp(i 4 pi f0 (v_i - v_ref) t_k / c),   t_k = tan(theta_k / 2),
+ * i.e. the plane's lateral column i is the other orientation's slice v_i.
+ * Reads the stage-1 slices that rca_beamform_stage1 left in `ws`.
+ *   proj_cross [2][B][F][Nz][Nu] c64, device, written.
+ * Needs nv == nu, dv == du and v0 == u0, nu <= 1024 and
+ * n_angles * nz * 8 <= 65536 (the transmits' slab profiles of a frame in LDS).
+ * Errors: INVALID_ARG (grid, NULL pointer, ws too small), HIP.
+ */
+int32_t rca_beamform_cross(ulm_ctx_t *ctx, float *proj_cross, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/*
+ * XDoppler image (Section II-A4: cross-correlation of the filtered RC and CR
+ * stacks with a window of `window` frames, 3 in the paper):
+ *   X_f = sum_{t = f - h .. f + h, 0 <= t < F} native_t * conj(cross_t),  h = (window - 1) / 2,
+ *   out[o][b][f][z][u] = (sqrt(|X_f|), 0)
+ * sqrt(|X|) is, for one microbubble, the geometric mean of its two
+ * orientations' amplitudes, so the localisers' template applies unchanged;
+ * ncc_localize and ulm_cnn_localize take `out` as their filtered planes.
+ *   native, cross [2][B][F][Nz][Nu] c64, device: the filtered projections and
+ *                 cross projections (svd_clutter_filter on each).
+ *   out           [2][B][F][Nz][Nu] c64, device; may be `native` itself (in
+ *                 place), must not overlap `cross`.
+ *   window        odd, in [1, 9].
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t ulm_xdoppler(ulm_ctx_t *ctx, const float *native, const float *cross, int32_t window,
+                     float *out, void *stream);
+
+/*
  * Eigen-based SVD clutter filter of every plane (Section II-A2), in place.
  *   proj    [2][B][F][Nz*Nu] c64, device, in/out.  Each plane's Casorati matrix
  *           I (pixels x frames) becomes I - (I V_c) V_c^H, V_c the eigenvectors of
  *           the svd_cutoff largest eigenvalues of C = I^H I (FP64 eigensolver).
  *   eigvals [2][B][F] f64, device, may be NULL: eigenvalues of C, descending.
+ * The context's precision selects how C and I V_c, (I V_c) V_c^H are formed:
+ * ULM_PREC_FP64GRAM on FP64 MFMA / FP64 FMAs, ULM_PREC_BF16X3 on BF16 MFMA with
+ * three-term split operands (see above); the eigensolver is FP64 in both.
  * A plane with a non-finite covariance is left unfiltered and flags the status
  * word (see ulm_check_status).  Errors: INVALID_ARG, HIP.
  */

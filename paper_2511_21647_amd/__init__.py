@@ -14,7 +14,7 @@ from ._lib import (ULM_OK, ULM_ERR_INVALID_ARG, ULM_ERR_HIP, ULM_ERR_OVERFLOW, U
                    ulm_cnn_workspace_size,
                    LOC_DTYPE, ULM_PREC_BF16X3, ULM_PREC_FP64GRAM, Context, ULMConfig, ULMError,
                    locs_to_numpy, make_config, ncc_localize, rca_beamform_proj, rca_beamform_stage1,
-                   rca_beamform_stage2, svd_clutter_filter,
+                   rca_beamform_stage2, rca_beamform_cross, ulm_xdoppler, svd_clutter_filter,
                    ulm_check_status, ulm_density_accumulate, ulm_reconstruct_ensemble,
                    ulm_sim_channel_data, LIB_PATH)
 
@@ -24,6 +24,7 @@ __all__ = ["ULM_OK", "ULM_ERR_INVALID_ARG", "ULM_ERR_HIP", "ULM_ERR_OVERFLOW", "
            "ulm_pair_planes_noalloc", "ULM_NOALLOC_SCRATCH_BYTES",
            "LOC_DTYPE", "ULM_PREC_BF16X3", "ULM_PREC_FP64GRAM", "Context", "ULMConfig",
            "ULMError", "locs_to_numpy", "make_config", "ncc_localize", "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2",
+           "rca_beamform_cross", "ulm_xdoppler",
            "svd_clutter_filter", "ulm_check_status", "ulm_density_accumulate",
            "ulm_reconstruct_ensemble", "ulm_sim_channel_data", "LIB_PATH",
            "CNN_LAYOUT", "CNN_THRESHOLD", "CNN_UPSAMPLE", "ULM_CNN_BF16", "ULM_CNN_FP32", "ULM_CNN_PARAMS",

@@ -39,7 +39,7 @@ CNN_LAYOUT = ([("w0", (32, 1, 3, 3)), ("b0", (32,))]
               + [("wh", (64, 32)), ("bh", (64,))])
 
 EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
-           "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
+           "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "rca_beamform_cross", "ulm_xdoppler", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
            "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
            "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
            "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize",
@@ -105,6 +105,8 @@ def _load():
         "rca_beamform_proj": ([vp, vp, vp, vp, sz, vp], i32),
         "rca_beamform_stage1": ([vp, vp, vp, sz, vp], i32),
         "rca_beamform_stage2": ([vp, vp, vp, sz, vp], i32),
+        "rca_beamform_cross": ([vp, vp, vp, sz, vp], i32),
+        "ulm_xdoppler": ([vp, vp, vp, i32, vp, vp], i32),
         "svd_clutter_filter": ([vp, vp, vp, vp, sz, vp], i32),
         "ncc_localize": ([vp, vp, vp, i32, vp, vp, sz, vp], i32),
         "ulm_reconstruct_ensemble": ([vp, vp, vp, vp, vp, i32, vp, vp, sz,
@@ -287,6 +289,32 @@ def rca_beamform_stage2(ctx: Context, proj=None, stream=None):
     _check(_lib.rca_beamform_stage2(ctx.handle, _ptr(proj), ctx.ws_ptr, ctx.ws_bytes,
                                     _stream(stream)))
     return proj
+
+
+def rca_beamform_cross(ctx: Context, cross=None, stream=None):
+    """Cross projections [2][B][F][Nz][Nu] (each plane gets the other orientation's
+    volume) from the reference slices held in the workspace."""
+    torch = _torch()
+    if cross is None:
+        cross = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=ctx.device)
+    _require(cross, torch.complex64, ctx.proj_shape, "cross")
+    _check(_lib.rca_beamform_cross(ctx.handle, _ptr(cross), ctx.ws_ptr, ctx.ws_bytes,
+                                   _stream(stream)))
+    return cross
+
+
+def ulm_xdoppler(ctx: Context, native, cross, window: int = 3, out=None, stream=None):
+    """XDoppler image (sqrt of the windowed |native conj(cross)|, zero imaginary
+    part) [2][B][F][Nz][Nu]; `out` may be `native` (in place)."""
+    torch = _torch()
+    _require(native, torch.complex64, ctx.proj_shape, "native")
+    _require(cross, torch.complex64, ctx.proj_shape, "cross")
+    if out is None:
+        out = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=native.device)
+    _require(out, torch.complex64, ctx.proj_shape, "out")
+    _check(_lib.ulm_xdoppler(ctx.handle, _ptr(native), _ptr(cross), int(window), _ptr(out),
+                             _stream(stream)))
+    return out
 
 
 def svd_clutter_filter(ctx: Context, proj, eigvals=None, stream=None):

@@ -42,6 +42,11 @@ hipError_t launch_separate(const ulm_ctx *ctx, const float2 *P, int n_speed, flo
                            hipStream_t st);
 size_t cnn_loc_workspace_bytes(int batch, int H, int W, int n_img, bool fp32);
 hipError_t scratch_init(int device);
+bool cross_supported(const Geometry &g, int per);
+hipError_t launch_cross(const ulm_ctx *ctx, const float2 *slices, float2 *prof, float2 *Q,
+                        hipStream_t st);
+hipError_t launch_xdoppler(const ulm_ctx *ctx, const float2 *P, const float2 *Q, int window,
+                           float2 *out, hipStream_t st);
 void *scratch_ptr(int device);
 hipError_t cnn_images(const float2 *P, const float *fmax, float *x0, int npix, int n0, int nb,
                       hipStream_t st);
@@ -81,7 +86,8 @@ extern "C" const char *ulm_last_error(void) { return g_err.c_str(); }
 
 static void free_tables(ulm_ctx *ctx) {
     Tables &t = ctx->tab;
-    void *ptrs[] = {t.stx, t.sti, t.phz, t.rxd, t.rxp, t.win, t.taps, t.tap_meta, t.angles, t.sep_tw};
+    void *ptrs[] = {t.stx, t.sti, t.phz, t.rxd, t.rxp, t.win, t.taps, t.tap_meta, t.angles, t.sep_tw,
+                    t.xd_n, t.xd_w};
     for (void *p : ptrs) (void)hipFree(p);
 }
 
@@ -111,6 +117,12 @@ static int32_t validate(const ulm_config_t &c) {
     return ULM_OK;
 }
 
+// the cross projection (XDoppler) needs the v grid to equal the u grid: the
+// plane's lateral axis is then the other orientation's v axis
+static bool square_grid(const ulm_config_t &c) {
+    return c.nv == c.nu && c.dv == c.du && c.v0 == c.u0;
+}
+
 static void layout_workspace(ulm_ctx *ctx) {
     const ulm_config_t &c = ctx->cfg;
     Workspace &w = ctx->ws;
@@ -136,6 +148,13 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.evals = take(sizeof(double) * planes * F);
     w.evecs = take(sizeof(double2) * planes * F * cc);
     w.vpad = take(sizeof(double2) * planes * F * removal_cols(c.svd_cutoff));
+    if (c.precision == ULM_PREC_BF16X3 && c.svd_cutoff > 0) {
+        const RemovalDims rd = removal_dims(c.n_frames, c.svd_cutoff);
+        w.rtab = take(16 * planes * (rd.t1_plane + rd.t2_plane));
+    } else {
+        w.rtab = take(0);
+    }
+    w.xprof = take(square_grid(c) ? sizeof(float2) * 2 * c.n_angles * c.n_blocks * F * c.nz : 0);
     w.tscratch = take(sizeof(double) * planes * cc * 6 * F);
     w.xscratch = take(sizeof(double2) * planes * cc * F);
     w.hvec = take(sizeof(double2) * planes * F * F);
@@ -358,6 +377,36 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
                 return cleanup(e, "hipMemcpy");
         }
     }
+    if (square_grid(c)) {
+        // cross projection: column i of the other orientation's volume is its
+        // reference slice moved by d = (v_i - v_ref) t_k / dz rows and turned by
+        // exp(i 4 pi f0 (v_i - v_ref) t_k / c) (stage 2's shift law)
+        std::vector<int> xn((size_t)c.n_angles * c.nu);
+        std::vector<float4> xw((size_t)c.n_angles * c.nu);
+        for (int k = 0; k < c.n_angles; ++k) {
+            const double tk = tan(0.5 * c.angles_rad[k]);
+            for (int i = 0; i < c.nu; ++i) {
+                const double dv = c.v0 + i * c.dv - c.v_ref;
+                const double d = dv * tk / c.dz;
+                const double fl = floor(d);
+                const double fr = d - fl;
+                const double ph = 4.0 * M_PI * c.f0 * dv * tk / c.c;
+                const double er = cos(ph), ei = sin(ph);
+                xn[(size_t)k * c.nu + i] = (int)fl;
+                if (k == 0 && i == 0) ctx->tab.xd_nmin = ctx->tab.xd_nmax = (int)fl;
+                ctx->tab.xd_nmin = std::min(ctx->tab.xd_nmin, (int)fl);
+                ctx->tab.xd_nmax = std::max(ctx->tab.xd_nmax, (int)fl);
+                xw[(size_t)k * c.nu + i] = make_float4((float)((1.0 - fr) * er), (float)((1.0 - fr) * ei),
+                                                       (float)(fr * er), (float)(fr * ei));
+            }
+        }
+        if ((e = hipMalloc(&ctx->tab.xd_n, sizeof(int) * xn.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+        if ((e = hipMalloc(&ctx->tab.xd_w, sizeof(float4) * xw.size())) != hipSuccess) return cleanup(e, "hipMalloc");
+        if ((e = hipMemcpy(ctx->tab.xd_n, xn.data(), sizeof(int) * xn.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return cleanup(e, "hipMemcpy");
+        if ((e = hipMemcpy(ctx->tab.xd_w, xw.data(), sizeof(float4) * xw.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return cleanup(e, "hipMemcpy");
+    }
     int lds_max = 0;
     if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device)) != hipSuccess)
         return cleanup(e, "hipDeviceGetAttribute");
@@ -424,6 +473,35 @@ extern "C" int32_t rca_beamform_proj(ulm_ctx_t *ctx, const float *iq, float *pro
     if (!iq || !proj) return fail(ULM_ERR_INVALID_ARG, "NULL iq or proj");
     if ((rc = rca_beamform_stage1(ctx, iq, ws, ws_bytes, stream))) return rc;
     return rca_beamform_stage2(ctx, proj, ws, ws_bytes, stream);
+}
+
+extern "C" int32_t rca_beamform_cross(ulm_ctx_t *ctx, float *proj_cross, void *ws, size_t ws_bytes,
+                                      void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!proj_cross) return fail(ULM_ERR_INVALID_ARG, "NULL cross-projection buffer");
+    if (!square_grid(ctx->cfg))
+        return fail(ULM_ERR_INVALID_ARG, "the cross projection needs the v grid equal to the u grid");
+    if (!cross_supported(ctx->geo, cdiv(ctx->geo.nu, ctx->geo.n_blocks)))
+        return fail(ULM_ERR_INVALID_ARG,
+                    "cross projection: plane width above 1024 or n_angles x nz x 8 bytes above 64 KiB");
+    HIP_TRY(launch_cross(ctx, (const float2 *)((char *)ws + ctx->ws.slices),
+                         (float2 *)((char *)ws + ctx->ws.xprof), (float2 *)proj_cross,
+                         (hipStream_t)stream),
+            "rca_beamform_cross");
+    return ULM_OK;
+}
+
+extern "C" int32_t ulm_xdoppler(ulm_ctx_t *ctx, const float *native, const float *cross,
+                                int32_t window, float *out, void *stream) {
+    if (!ctx || !native || !cross || !out) return fail(ULM_ERR_INVALID_ARG, "NULL argument");
+    if (window < 1 || window > 9 || (window & 1) == 0)
+        return fail(ULM_ERR_INVALID_ARG, "window must be odd, in [1, 9]");
+    if (out == cross) return fail(ULM_ERR_INVALID_ARG, "out may alias the native stack, not the cross stack");
+    HIP_TRY(launch_xdoppler(ctx, (const float2 *)native, (const float2 *)cross, window, (float2 *)out,
+                            (hipStream_t)stream),
+            "ulm_xdoppler");
+    return ULM_OK;
 }
 
 extern "C" int32_t svd_clutter_filter(ulm_ctx_t *ctx, float *proj, double *eigvals, void *ws,

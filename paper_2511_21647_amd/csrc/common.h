@@ -26,6 +26,29 @@ constexpr int kGramStage = 32;     // pixels staged in LDS per step
 constexpr int kNccBand = 16;       // NCC output rows per work-group
 constexpr int kNccMaxHalf = 7;     // template half-width limit (size <= 15)
 
+// Split-precision clutter filter: BF16 terms per operand (x = hi + mid + lo),
+// and the shape of the removal's per-plane MFMA operand tables (built from the
+// clutter eigenvectors), counted in 16-byte lane operands (8 BF16 values).
+constexpr int kSplitTerms = 3;
+struct RemovalDims {
+    int MT;            // 32-row tiles of the 2c real rows of (I V_c)^T
+    int S1;            // K-steps (8 frames each) of I V_c
+    int FT;            // 32-frame tiles of the output
+    int KT2;           // K-steps (16 real rows each) of (I V_c) V_c^H
+    size_t t1_plane;   // lane operands per plane, first product
+    size_t t2_plane;   // lane operands per plane, second product
+};
+inline RemovalDims removal_dims(int F, int c) {
+    RemovalDims d;
+    d.MT = (2 * c + 31) / 32;
+    d.S1 = (F + 7) / 8;
+    d.FT = (F + 31) / 32;
+    d.KT2 = (2 * c + 15) / 16;
+    d.t1_plane = (size_t)d.MT * d.S1 * kSplitTerms * 64;
+    d.t2_plane = (size_t)d.FT * d.KT2 * 2 * kSplitTerms * 64;
+    return d;
+}
+
 // Status bits written to the workspace status word.
 constexpr int kStatusNumeric = 1;   // a plane's covariance was not finite: plane left unfiltered
 constexpr int kStatusBarrier = 2;   // the eigensolver's inter-work-group wait timed out
@@ -53,6 +76,10 @@ struct Tables {
     int n_taps;        // maximum taps over (transmit, block)
     int fir_group;     // slabs per stage-2 work-group: 1 or kFirGroup
     float2 *sep_tw;    // MB-separation FFT twiddles for F frames (null if F has a factor > 7)
+    int *xd_n;         // [K][Nu] cross projection: integer part of the axial shift of column i
+    float4 *xd_w;      // [K][Nu] ((1 - frac) e, frac e), e = the column's stage-2 phase
+                       // (both null unless the v grid equals the u grid)
+    int xd_nmin, xd_nmax;   // range of xd_n
 };
 
 // Words per plane of the eigensolver's barrier area: one grid-barrier flag per
@@ -71,6 +98,8 @@ struct Workspace {
     size_t evals;       // [planes][F] f64          descending
     size_t evecs;       // [planes][F][c] c128
     size_t vpad;        // [planes][F][removal_cols(c)] c128, zero past column c
+    size_t rtab;        // [planes][t1_plane + t2_plane] BF16 x 8 operands (split removal only)
+    size_t xprof;       // [2][K][B][F][Nz] c64 slab sums of the stage-1 slices (cross projection)
     size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
     size_t xscratch;    // [planes][c][F] c128      back-transformed vectors
     size_t hvec;        // [planes][F][F] c128      Householder vectors

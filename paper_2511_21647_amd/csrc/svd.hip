@@ -20,6 +20,7 @@ namespace ulm {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline void pair_of(int pair, int nblk, int &I, int &J) {
     int p = pair;
@@ -135,17 +136,92 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
             }
 }
 
-// ---------------------------------------------------------------- Gram, BF16 split
-// Split-precision form: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the
-// products hi.hi + hi.lo + lo.hi run on v_mfma_f32_32x32x16_bf16 with FP32
-// accumulation.  The FP32 accumulators are folded into FP64 after every staged
-// group of pixels.  One wave per 32x32 quadrant; K = 16 = 8 pixels x (re, im).
-__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+// Three-term BF16 split of a value (hi, mid, lo).
+struct bf16x3 { __bf16 h, m, l; };
 
-__global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float2 *__restrict__ P,
-                                                          double2 *__restrict__ part, int F,
-                                                          int npix, int pairs, int chunks, int nblk)
+__device__ inline bf16x3 split3(float x) {
+    bf16x3 o;
+    o.h = (__bf16)x;
+    float r = x - (float)o.h;      // exact
+    o.m = (__bf16)r;
+    r -= (float)o.m;               // exact
+    o.l = (__bf16)r;
+    return o;
+}
+
+__device__ inline bf16x3 split3(double x) {
+    bf16x3 o;
+    o.h = (__bf16)(float)x;
+    double r = x - (double)(float)o.h;
+    o.m = (__bf16)(float)r;
+    r -= (double)(float)o.m;
+    o.l = (__bf16)(float)r;
+    return o;
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+struct bf16x2x3 { bf16x2 h, m, l; };
+
+// Three-term split of two floats at once (one packed conversion per term).
+__device__ inline bf16x2x3 split3x2(f32x2 x) {
+    bf16x2x3 o;
+    o.h = __builtin_convertvector(x, bf16x2);
+    f32x2 r = x - __builtin_convertvector(o.h, f32x2);     // exact
+    o.m = __builtin_convertvector(r, bf16x2);
+    r -= __builtin_convertvector(o.m, f32x2);              // exact
+    o.l = __builtin_convertvector(r, bf16x2);
+    return o;
+}
+
+__device__ inline bf16x8 cat4(bf16x2 a, bf16x2 b, bf16x2 c, bf16x2 d) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    const bf16x4 ab = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+    const bf16x4 cd = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+    return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// element j of the three term vectors t[0..2] <- the terms of x
+#define ULM_SET3(t, j, x)        \
+    do {                         \
+        const bf16x3 s3_ = split3(x); \
+        (t)[0][j] = s3_.h;       \
+        (t)[1][j] = s3_.m;       \
+        (t)[2][j] = s3_.l;       \
+    } while (0)
+
+// ---------------------------------------------------------------- Gram, BF16 split
+// Split-precision form: every value is a sum of kSplitTerms = 3 BF16 terms,
+// x = hi + mid + lo (hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi -
+// mid): exact for FP32 data), and the products of terms whose orders add up
+// to less than three (hi.hi, hi.mid, mid.hi, hi.lo, mid.mid, lo.hi) run on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  (Two terms with hi.hi +
+// hi.lo + lo.hi leave a relative error of 2^-17 per product; where the
+// clutter eigenvalues span four decades that moves the filtered planes by
+// about 1e-3.)  The complex Gram is formed from real products of the real and
+// imaginary planes: with a = row f1, b = row f2 of the stack,
+//   C_re = a_re . b_re + a_im . b_im,   C_im = a_re . b_im - a_im . b_re,
+// K = 16 pixels per instruction.  Each element is split once, when the
+// work-group stages it: a thread loads eight consecutive pixels of a frame
+// (prefetched one stage ahead), splits them and writes six 16-byte BF16 rows
+// (re hi, mid, lo, im hi, mid, lo) to LDS, which is double-buffered, so a
+// stage needs one barrier and its inner loop only reads LDS and issues MFMAs.
+// The imaginary part takes a_im with its sign bits flipped, so a stage has two
+// FP32 accumulators, which are added into FP64 after every stage: the FP32
+// rounding then applies to 16-pixel partial sums only, not to the running
+// covariance (an FP32 running sum would leave a relative error near 1e-7 in
+// C and, amplified by the eigenvalue spread, about 1e-4 in the filtered
+// planes).  One wave per 32x32 quadrant of the 64x64 block pair.
+constexpr int kG16Stage = 16;                    // pixels per stage (one K-step)
+constexpr int kG16Pitch = kG16Stage + 8;         // BF16 per LDS row (padded against bank conflicts)
+constexpr int kG16Rows = 2 * kGramBlock;         // frames of the two blocks
+
+__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(const float2 *__restrict__ P,
+                                                             double2 *__restrict__ part, int F,
+                                                             int npix, int pairs, int chunks,
+                                                             int nblk)
 {
+    constexpr int NT = kSplitTerms;
     const int chunk = blockIdx.x % chunks;
     const int pair = (blockIdx.x / chunks) % pairs;
     const int plane = blockIdx.x / (chunks * pairs);
@@ -155,64 +231,121 @@ __global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float2 *__restri
     const int px0 = chunk * kGramChunk;
     const int px1 = min(px0 + kGramChunk, npix);
 
-    __shared__ float2 lds[2 * kGramBlock][kGramStage + 1];
+    // [buffer][re terms 0..NT-1, im terms 0..NT-1][row][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 lds[2][2 * NT][kG16Rows][kG16Pitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi = wave >> 1, wj = wave & 1;
     const int half = lane >> 5, r32 = lane & 31;
 
+    // staging: thread t owns pixels (t % 2) * 8 .. + 7 of row t / 2
+    const int sg = threadIdx.x & 1, srow = threadIdx.x >> 1;
+    const int sframe = srow < kGramBlock ? I * kGramBlock + srow : J * kGramBlock + srow - kGramBlock;
+    const float2 *srcrow = src + (size_t)min(sframe, F - 1) * npix;
+    float2 pre[8];
+    auto fetch = [&](int p0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int px = p0 + sg * 8 + q;
+            const float2 v = srcrow[min(px, px1 - 1)];
+            pre[q] = (sframe < F && px < px1) ? v : make_float2(0.f, 0.f);
+        }
+    };
+    auto stage = [&](int buf) {
+        // pixels 2p, 2p + 1 split together
+        bf16x2x3 re[4], im[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            re[p] = split3x2(f32x2{pre[2 * p].x, pre[2 * p + 1].x});
+            im[p] = split3x2(f32x2{pre[2 * p].y, pre[2 * p + 1].y});
+        }
+        bf16x8 *row = reinterpret_cast<bf16x8 *>(&lds[buf][0][srow][sg * 8]);
+        constexpr int kPlane = kG16Rows * kG16Pitch / 8;       // bf16x8 per term plane
+        row[0 * kPlane] = cat4(re[0].h, re[1].h, re[2].h, re[3].h);
+        row[1 * kPlane] = cat4(re[0].m, re[1].m, re[2].m, re[3].m);
+        row[2 * kPlane] = cat4(re[0].l, re[1].l, re[2].l, re[3].l);
+        row[3 * kPlane] = cat4(im[0].h, im[1].h, im[2].h, im[3].h);
+        row[4 * kPlane] = cat4(im[0].m, im[1].m, im[2].m, im[3].m);
+        row[5 * kPlane] = cat4(im[0].l, im[1].l, im[2].l, im[3].l);
+    };
+
     double dr[16], di[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) dr[q] = di[q] = 0.0;
+    // two sets of FP32 accumulators: a stage's products go to one set while the
+    // other set (the previous stage's) is added into FP64, so the additions
+    // wait on no MFMA in flight.  The loop body has no branch, so the compiler
+    // interleaves the staging of the next pixels with the MFMAs.  (In a diagonal
+    // block the lower-left quadrant's wave computes the mirror of the
+    // upper-right one, which the reduction does not read.)
+    f32x16 s0re = {}, s0im = {}, s1re = {}, s1im = {};
 
-    for (int p0 = px0; p0 < px1; p0 += kGramStage) {
-        for (int e = threadIdx.x; e < 2 * kGramBlock * kGramStage; e += 256) {
-            const int row = e / kGramStage, col = e % kGramStage;
-            const int frame = row < kGramBlock ? I * kGramBlock + row : J * kGramBlock + row - kGramBlock;
-            const int px = p0 + col;
-            float2 v = make_float2(0.f, 0.f);
-            if (frame < F && px < px1) v = src[(size_t)frame * npix + px];
-            lds[row][col] = v;
+    const int arow = wi * 32 + r32, brow = kGramBlock + wj * 32 + r32;
+    const int col = half * 8;
+    auto products = [&](int b, f32x16 &c_re, f32x16 &c_im) {
+        bf16x8 ar[NT], ai[NT], br[NT], bi[NT], nai[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            ar[k] = *reinterpret_cast<const bf16x8 *>(&lds[b][k][arow][col]);
+            ai[k] = *reinterpret_cast<const bf16x8 *>(&lds[b][NT + k][arow][col]);
+            br[k] = *reinterpret_cast<const bf16x8 *>(&lds[b][k][brow][col]);
+            bi[k] = *reinterpret_cast<const bf16x8 *>(&lds[b][NT + k][brow][col]);
+            // -a_im: the sign bits flipped
+            u32x4 bits = __builtin_bit_cast(u32x4, ai[k]);
+            bits ^= 0x80008000u;
+            nai[k] = __builtin_bit_cast(bf16x8, bits);
         }
-        __syncthreads();
-        f32x16 cr = {}, ci = {};
+        // smallest products first, hi.hi last: the FP32 partial sums stay small
+        // until the last two instructions, so most roundings are relative to
+        // small values
 #pragma unroll
-        for (int step = 0; step < kGramStage / 8; ++step) {
-            // lane holds k = half*8 + [0, 8): pixels step*8 + half*4 + [0, 4), (re, im) each
-            bf16x8 ahi, alo, bhi, blo, bihi, bilo;
+        for (int ord = NT - 1; ord >= 0; --ord)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int pxl = step * 8 + half * 4 + q;
-                const float2 va = lds[wi * 32 + r32][pxl];
-                const float2 vb = lds[kGramBlock + wj * 32 + r32][pxl];
-                const __bf16 ar = to_bf16(va.x), ai = to_bf16(va.y);
-                const __bf16 br = to_bf16(vb.x), bi = to_bf16(vb.y);
-                ahi[2 * q] = ar;  alo[2 * q] = to_bf16(va.x - (float)ar);
-                ahi[2 * q + 1] = ai;  alo[2 * q + 1] = to_bf16(va.y - (float)ai);
-                bhi[2 * q] = br;  blo[2 * q] = to_bf16(vb.x - (float)br);
-                bhi[2 * q + 1] = bi;  blo[2 * q + 1] = to_bf16(vb.y - (float)bi);
-                // B' = (im, -re)
-                bihi[2 * q] = bi;  bilo[2 * q] = blo[2 * q + 1];
-                bihi[2 * q + 1] = to_bf16(-vb.x);  bilo[2 * q + 1] = to_bf16(-(vb.x - (float)br));
+            for (int ta = 0; ta <= ord; ++ta) {
+                const int tb = ord - ta;
+                c_re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ta], br[tb], c_re, 0, 0, 0);
+                c_re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ta], bi[tb], c_re, 0, 0, 0);
+                c_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ta], bi[tb], c_im, 0, 0, 0);
+                c_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nai[ta], br[tb], c_im, 0, 0, 0);
             }
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bihi, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bilo, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bihi, ci, 0, 0, 0);
-        }
+    };
+    // the 16 pixels' sums, rounded in FP32, are added in FP64
+    auto fold = [&](f32x16 &c_re, f32x16 &c_im) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) { dr[q] += cr[q]; di[q] += ci[q]; }
+        for (int q = 0; q < 16; ++q) {
+            dr[q] += (double)c_re[q];
+            di[q] += (double)c_im[q];
+        }
+        c_re = f32x16{};
+        c_im = f32x16{};
+    };
+
+    fetch(px0);
+    stage(0);
+    __syncthreads();
+    // stages n (buffer 0, set 0) and n + 1 (buffer 1, set 1) per iteration;
+    // past the chunk's end the staged pixels are zeros, so an odd stage count
+    // runs one stage of zeros
+    for (int p0 = px0; p0 < px1; p0 += 2 * kG16Stage) {
+        fetch(p0 + kG16Stage);
+        products(0, s0re, s0im);
+        fold(s1re, s1im);
+        stage(1);
+        __syncthreads();
+        fetch(p0 + 2 * kG16Stage);
+        products(1, s1re, s1im);
+        fold(s0re, s0im);
+        stage(0);
         __syncthreads();
     }
+    fold(s1re, s1im);
 
     double2 *dst = part + ((size_t)(plane * pairs + pair) * chunks + chunk) * kGramBlock * kGramBlock;
     // 32x32 output layout: acc q -> row 8*(q/4) + 4*half + q%4, column r32
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int row = wi * 32 + 8 * (q >> 2) + 4 * half + (q & 3);
-        const int col = wj * 32 + r32;
-        dst[row * kGramBlock + col] = make_double2(dr[q], di[q]);
+        const int cc = wj * 32 + r32;
+        dst[row * kGramBlock + cc] = make_double2(dr[q], di[q]);
     }
 }
 
@@ -671,6 +804,201 @@ __global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
     }
 }
 
+// ---------------------------------------------------------------- removal, BF16 split
+// Split-precision form of I_f = I - (I V_c) V_c^H on v_mfma_f32_32x32x16_bf16.
+// A wave owns 32 pixels and forms both products transposed, so that the pixel
+// is the MFMA's N index (lanes read and write consecutive pixels):
+//   Y^T   = W1 X^T         rows 2i, 2i+1 = (re, im) of (I V_c)[p][i];
+//                          K = (frame, re/im), 8 frames per K-step
+//   X_f^T = X^T - W2 Y^T   rows = frames (one real, one imaginary accumulator);
+//                          K = the 2c real rows of Y^T
+// W1 and W2 hold the clutter eigenvectors arranged as MFMA A operands, built
+// per plane by removal_tables_kernel.  Every operand is a sum of kSplitTerms = 3
+// BF16 terms (hi + mid + lo, exact for FP32 data); the products of terms whose
+// orders add up to less than three are accumulated in FP32, and the first
+// product's accumulators are added into FP64 after every K-step.  The first
+// product's output feeds the second product's B operand from registers: a
+// lane's accumulator q holds row 8 (q / 4) + 4 half + q % 4 of its 32-row
+// tile, so K-step t of the second product (tile t / 2, half t % 2) takes
+// accumulators 8 (t % 2) .. 8 (t % 2) + 7, and W2 orders its K index alike.
+
+
+
+// One thread per (plane, table entry, lane): the 8 BF16 values of the lane's
+// operand, in kSplitTerms terms.
+__global__ void removal_tables_kernel(const double2 *__restrict__ V, bf16x8 *__restrict__ tab,
+                                      int F, int c, RemovalDims d, int planes)
+{
+    constexpr int NT = kSplitTerms;
+    const size_t n1 = (size_t)d.MT * d.S1 * 64, n2 = (size_t)d.FT * d.KT2 * 2 * 64;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)planes * (n1 + n2)) return;
+    const int plane = (int)(idx / (n1 + n2));
+    const size_t e = idx % (n1 + n2);
+    const double2 *Vp = V + (size_t)plane * F * c;
+    bf16x8 *out = tab + (size_t)plane * (d.t1_plane + d.t2_plane);
+    const int lane = (int)(e % 64), h = lane >> 5, row = lane & 31;
+    double val[8];
+    size_t base;
+    if (e < n1) {
+        // W1: row m = (i, part), K index j = (frame 8 s + 4 h + j / 2, re/im j % 2)
+        const int s = (int)((e / 64) % d.S1), mt = (int)(e / (64 * (size_t)d.S1));
+        const int m = 32 * mt + row, i = m >> 1, part = m & 1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int g = 8 * s + 4 * h + (j >> 1), ri = j & 1;
+            double x = 0.0;
+            if (i < c && g < F) {
+                const double2 v = Vp[(size_t)g * c + i];
+                // Y_re = sum x_re v_re - x_im v_im,  Y_im = sum x_re v_im + x_im v_re
+                x = part == 0 ? (ri == 0 ? v.x : -v.y) : (ri == 0 ? v.y : v.x);
+            }
+            val[j] = x;
+        }
+        base = ((size_t)mt * d.S1 + s) * NT * 64 + lane;
+    } else {
+        // W2: row = frame f, K index j = row r of Y^T (see above); ro = 0 real
+        // output, 1 imaginary output
+        const size_t e2 = e - n1;
+        const int ro = (int)((e2 / 64) % 2), t = (int)((e2 / 128) % d.KT2);
+        const int ft = (int)(e2 / (128 * (size_t)d.KT2));
+        const int f = 32 * ft + row, mt = t >> 1, tl = t & 1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int r = 32 * mt + 8 * (2 * tl + (j >> 2)) + 4 * h + (j & 3);
+            const int i = r >> 1, part = r & 1;
+            double x = 0.0;
+            if (i < c && f < F) {
+                const double2 v = Vp[(size_t)f * c + i];
+                // (Y conj(v))_re = Y_re v_re + Y_im v_im,  _im = Y_im v_re - Y_re v_im
+                x = ro == 0 ? (part == 0 ? v.x : v.y) : (part == 0 ? -v.y : v.x);
+            }
+            val[j] = x;
+        }
+        base = d.t1_plane + (((size_t)ft * d.KT2 + t) * 2 + ro) * NT * 64 + lane;
+    }
+    bf16x8 o[NT];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ULM_SET3(o, j, val[j]);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) out[base + (size_t)k * 64] = o[k];
+}
+
+template <int MT>
+__global__ __launch_bounds__(256) void removal_bf16_kernel(float2 *__restrict__ P,
+                                                           const bf16x8 *__restrict__ tab, int F,
+                                                           int npix, RemovalDims d,
+                                                           const int *__restrict__ eflag)
+{
+    constexpr int NT = kSplitTerms;
+    const int plane = blockIdx.y;
+    if (eflag[plane]) return;      // non-finite covariance: the plane stays unfiltered
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, n = lane & 31;
+    const int p0 = (blockIdx.x * 4 + wave) * 32;
+    if (p0 >= npix) return;
+    const int p = p0 + n;
+    const bool pin = p < npix;
+    const int pc = pin ? p : npix - 1;
+    float2 *X = P + (size_t)plane * F * npix;
+    const bf16x8 *t1 = tab + (size_t)plane * (d.t1_plane + d.t2_plane) + lane;
+    const bf16x8 *t2 = t1 + d.t1_plane;
+
+    // first product, Y^T = W1 X^T: this lane's B operand at K-step s is
+    // frames 8 s + 4 h + [0, 4) of pixel p, (re, im) each
+    double y[MT][16];
+    f32x16 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) y[mt][q] = 0.0;
+        acc[mt] = f32x16{};
+    }
+    float2 cur[4], nxt[4];
+    auto fetch = [&](int s, float2 *dst) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = 8 * s + 4 * h + q;
+            const float2 v = X[(size_t)min(g, F - 1) * npix + pc];
+            dst[q] = (g < F && pin) ? v : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(0, cur);
+    for (int s = 0; s < d.S1; ++s) {
+        if (s + 1 < d.S1) fetch(s + 1, nxt);
+        bf16x8 b[NT];
+        {
+            bf16x2x3 t[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] = split3x2(f32x2{cur[q].x, cur[q].y});
+            b[0] = cat4(t[0].h, t[1].h, t[2].h, t[3].h);
+            b[1] = cat4(t[0].m, t[1].m, t[2].m, t[3].m);
+            b[2] = cat4(t[0].l, t[1].l, t[2].l, t[3].l);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const bf16x8 *w = t1 + ((size_t)mt * d.S1 + s) * NT * 64;
+            bf16x8 a[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) a[k] = w[k * 64];
+#pragma unroll
+            for (int ord = NT - 1; ord >= 0; --ord)          // smallest products first
+#pragma unroll
+                for (int ta = 0; ta <= ord; ++ta)
+                    acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ta], b[ord - ta], acc[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) y[mt][q] += (double)acc[mt][q];
+            acc[mt] = f32x16{};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+    }
+
+    // second product, one 32-frame tile at a time: B operand of K-step t =
+    // accumulator rows 8 (t % 2) .. + 7 of tile t / 2, split into terms
+    bf16x8 b2[2 * MT][NT];
+#pragma unroll
+    for (int t = 0; t < 2 * MT; ++t)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            ULM_SET3(b2[t], j, y[t >> 1][8 * (t & 1) + j]);
+    for (int ft = 0; ft < d.FT; ++ft) {
+        float2 x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int f = 32 * ft + 8 * (q >> 2) + 4 * h + (q & 3);
+            x[q] = X[(size_t)min(f, F - 1) * npix + pc];
+        }
+        f32x16 are = {}, aim = {};
+#pragma unroll
+        for (int t = 0; t < 2 * MT; ++t) {
+            if (t >= d.KT2) break;
+            const bf16x8 *w = t2 + (((size_t)ft * d.KT2 + t) * 2) * NT * 64;
+            bf16x8 ar[NT], ai[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                ar[k] = w[k * 64];
+                ai[k] = w[(NT + k) * 64];
+            }
+#pragma unroll
+            for (int ord = NT - 1; ord >= 0; --ord)          // smallest products first
+#pragma unroll
+                for (int ta = 0; ta <= ord; ++ta) {
+                    are = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ta], b2[t][ord - ta], are, 0, 0, 0);
+                    aim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ta], b2[t][ord - ta], aim, 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int f = 32 * ft + 8 * (q >> 2) + 4 * h + (q & 3);
+            if (f < F && pin) X[(size_t)f * npix + p] = make_float2(x[q].x - are[q], x[q].y - aim[q]);
+        }
+    }
+}
+
 hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, char *ws,
                          hipStream_t st)
 {
@@ -733,7 +1061,20 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
                            (double2 *)(ws + w.xscratch), F, c, status, eigvals_out, (int *)(ws + w.eflag));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (c > 0) {
+    if (c > 0 && ctx->cfg.precision == ULM_PREC_BF16X3) {
+        const RemovalDims rd = removal_dims(F, c);
+        bf16x8 *tab = (bf16x8 *)(ws + w.rtab);
+        const size_t nthr = (size_t)planes * (rd.t1_plane + rd.t2_plane) / kSplitTerms;
+        hipLaunchKernelGGL(removal_tables_kernel, dim3((unsigned)cdiv<size_t>(nthr, 256)), dim3(256), 0,
+                           st, (const double2 *)(ws + w.evecs), tab, F, c, rd, planes);
+        dim3 grid(cdiv(npix, 128), planes);
+        const int *eflag = (const int *)(ws + w.eflag);
+        if (rd.MT == 1)
+            hipLaunchKernelGGL(removal_bf16_kernel<1>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag);
+        else
+            hipLaunchKernelGGL(removal_bf16_kernel<2>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (c > 0) {
         const int CM = removal_cols(c);
         double2 *Vp = (double2 *)(ws + w.vpad);
         hipLaunchKernelGGL(pad_subspace_kernel, dim3(cdiv(planes * F * CM, 256)), dim3(256), 0, st,

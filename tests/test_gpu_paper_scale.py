@@ -9,7 +9,7 @@ synthetic (never a library output)."""
 import numpy as np
 import pytest
 
-from synth import arrays, cfg_paper, with_frames
+from synth import arrays, cfg_paper, make_medium, with_frames
 from oracle import beamform, clutter, cnn, localize
 from gpu_util import compare_detections, rel_l2, say
 
@@ -204,3 +204,119 @@ def test_paper_cnn_forward_and_localize(torch, ulm, cfg):
                        int(round((float(r["u"]) + 0.5) * cnn.R - 0.5))) for r in mine)
         say(f"  plane {o} frame {f0}: threshold {thr:.4f}, {len(have)} peaks, decode rule {len(want)}")
         assert have == want and len(want) > 0
+
+
+def match_detections(a, b, radius=0.5):
+    """One-to-one matching of two detection lists of one image (arrays of (z, u)),
+    closest pairs first, within `radius` px.  Returns the matched distances."""
+    if len(a) == 0 or len(b) == 0:
+        return np.zeros(0)
+    d = np.hypot(a[:, None, 0] - b[None, :, 0], a[:, None, 1] - b[None, :, 1])
+    ia, ib = np.nonzero(d <= radius)
+    order = np.argsort(d[ia, ib], kind="stable")
+    used_a, used_b, out = set(), set(), []
+    for t in order:
+        i, j = int(ia[t]), int(ib[t])
+        if i in used_a or j in used_b:
+            continue
+        used_a.add(i)
+        used_b.add(j)
+        out.append(d[i, j])
+    return np.array(out)
+
+
+def test_paper_whole_path_simulated(torch, ulm, cfg):
+    """The paper-scale ensemble simulated by the library (2000 MBs on vessels,
+    tissue 40 dB above them, rigid motion, noise), through the whole path in the
+    launch configuration the bench times, against the oracle at every step:
+      - beamformed projections of three sampled frames against the oracle's
+        two-stage beamformer of those frames' channel data;
+      - both full filtered planes against the oracle's filter of the library's
+        own projections: plain form within 2e-5.  The split-precision form
+        states its error; here the cutoff falls between two nearly equal
+        eigenvalues (lambda_20 / lambda_21 about 1.02, with lambda_1 / lambda_20
+        about 4e6), so the clutter subspace moves with any covariance error
+        and even an exactly rounded FP32 covariance moves the filtered planes
+        by about 1e-2; the split form must do at least as well as that;
+      - NCC detections of three sampled frames of both planes against the
+        oracle's localiser on the library's filtered planes: identical
+        decidable sets, every decidable detection within 1e-3 px (the count
+        of undecidable candidates is reported);
+      - split-precision form: its NCC detections against the oracle's
+        detections on the oracle's FP64-filtered planes, matched one to one
+        within 0.5 px: recall >= 0.95 and RMS position error <= 0.1 px."""
+    med = make_medium(cfg, 0)
+    ctx = ulm.Context(cfg)
+    pos = _dev(torch, med.pos, torch.float64)
+    amp = torch.from_numpy(med.amp).cuda()
+    iq = ulm.ulm_sim_channel_data(ctx, pos, amp, med.noise_seed, med.noise_sigma)
+    del pos, amp
+    proj = ulm.rca_beamform_proj(ctx, iq)
+    torch.cuda.synchronize()
+    sub = iq[list(SAMPLE_FRAMES)].cpu().numpy()
+    del iq
+    say(f"[paper whole path] simulated {med.pos.shape[1]} scatterers, frames {SAMPLE_FRAMES}")
+    ref_p = beamform.beamform_proj(sub.astype(np.complex128), with_frames(cfg, len(SAMPLE_FRAMES)))
+    p = proj.cpu().numpy()
+    for o in range(2):
+        e = rel_l2(p[o][:, list(SAMPLE_FRAMES)], ref_p[o])
+        say(f"  beamformed plane {o}, sampled frames: rel-L2 {e:.2e}")
+        assert e <= BEAMFORM_TOL
+    ref_f, eig = clutter.filter_planes(p.astype(np.complex128), cfg.svd_cutoff)
+    cut = cfg.svd_cutoff
+    fp32_err = []
+    for o in range(2):
+        # the oracle's filter with its covariance rounded to FP32
+        x = clutter.casorati(p[o, 0].astype(np.complex128))
+        C32 = (x.conj().T @ x).astype(np.complex64).astype(np.complex128)
+        _, V = clutter.clutter_subspace(C32, cut)
+        f32 = (x - (x @ V) @ V.conj().T).T.reshape(p[o, 0].shape)
+        fp32_err.append(rel_l2(f32, ref_f[o, 0]))
+        say(f"  plane {o}: lambda_1/lambda_c {eig[o, 0, 0] / eig[o, 0, cut - 1]:.2e}, "
+            f"lambda_c/lambda_c+1 {eig[o, 0, cut - 1] / eig[o, 0, cut]:.4f}; filter with an FP32-rounded "
+            f"covariance: rel-L2 {fp32_err[-1]:.2e}")
+    forms = {}
+    for name, prec, tol in (("plain", ulm.ULM_PREC_FP64GRAM, [FILTER_TOL] * 2),
+                            ("bf16x3", ulm.ULM_PREC_BF16X3, fp32_err)):
+        c = ctx if prec == ulm.ULM_PREC_FP64GRAM else ulm.Context(cfg, precision=prec)
+        d = proj.clone()
+        ulm.svd_clutter_filter(c, d)
+        ulm.ulm_check_status(c)
+        locs, cnt = ulm.ncc_localize(c, d, capacity=4_000_000)
+        ulm.ulm_check_status(c, cnt, 4_000_000)
+        f = d.cpu().numpy()
+        for o in range(2):
+            e = rel_l2(f[o, 0], ref_f[o, 0])
+            say(f"  {name} filtered plane {o}: rel-L2 {e:.2e} against the oracle's filter")
+            assert e <= tol[o]
+        forms[name] = (f, ulm.locs_to_numpy(locs, cnt))
+        del d
+    # plain NCC against the oracle on the library's filtered planes
+    f, got = forms["plain"]
+    fr = list(SAMPLE_FRAMES)
+    ora, N, I = localize.localize(f[:, :, fr].astype(np.complex128), cfg)
+    sel = got[np.isin(got["frame"], fr)].copy()
+    sel["frame"] = np.searchsorted(np.array(fr), sel["frame"])
+    n, nund, err = compare_detections(sel, ora, N, I, cfg, 1e-5, POS_TOL)
+    say(f"  plain NCC, {len(fr)} frames x 2 planes: {n} decidable detections identical, "
+        f"{nund} undecidable, max position error {err:.1e} px")
+    # split-precision form against the oracle's FP64 chain
+    ora64, _, _ = localize.localize(ref_f[:, :, fr], cfg)
+    _, gotb = forms["bf16x3"]
+    nm = no = ng = 0
+    d2 = []
+    for o in range(2):
+        for i, fi in enumerate(fr):
+            a = ora64[(ora64["plane"] == o) & (ora64["frame"] == i)]
+            b = gotb[(gotb["plane"] == o) & (gotb["frame"] == fi)]
+            m = match_detections(np.stack([a["z"], a["u"]], 1), np.stack([b["z"], b["u"]], 1))
+            nm += len(m)
+            no += len(a)
+            ng += len(b)
+            d2 += list(m ** 2)
+    recall, precision = nm / max(no, 1), nm / max(ng, 1)
+    rms = float(np.sqrt(np.mean(d2))) if d2 else 0.0
+    say(f"  bf16x3 NCC vs the FP64 oracle chain: recall {recall:.4f}, precision {precision:.4f}, "
+        f"RMS {rms:.2e} px over {nm} matched of {no} oracle detections")
+    assert recall >= 0.95
+    assert rms <= 0.1

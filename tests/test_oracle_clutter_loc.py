@@ -1,4 +1,6 @@
 """Pins of the oracle's clutter filter and NCC localiser (CPU only)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -251,3 +253,26 @@ def test_ssim_brute_force_windows():
     assert abs(got - np.mean(vals)) < 1e-12
     assert abs(pipeline.ssim(b, a, data_range=R) - got) < 1e-13
     assert abs(pipeline.ssim(a.T, b.T, data_range=R) - got) < 1e-13
+
+
+def test_fp32_sensitivity_file_is_current():
+    """tests/golden/fp32_sensitivity_tiny.json (the oracle's own response to
+    FP32-sized errors in its input projections, which sets how close a whole-path
+    comparison with the FP32 GPU path can be) matches a fresh run of the script
+    that wrote it; FP32 rounding alone already moves decidable detections by a
+    few 1e-4 px, and the response grows with the input error."""
+    import importlib.util
+    import json
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "make_fp32_sensitivity.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    stored = json.load(open(os.path.join(here, "fp32_sensitivity_tiny.json")))
+    fresh = mk.measure()
+    assert stored["reference_detections"] == fresh["reference_detections"]
+    for name, vals in fresh["variants"].items():
+        for k, v in vals.items():
+            assert np.isclose(stored["variants"][name][k], v, rtol=1e-6, atol=0), (name, k)
+    r, p = fresh["variants"]["fp32"], fresh["variants"]["fp32_perturbed"]
+    assert 1e-5 < r["max_dpos_decidable_px"] < p["max_dpos_decidable_px"]
+    assert r["max_abs_dncc"] < p["max_abs_dncc"]

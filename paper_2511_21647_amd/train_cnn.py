@@ -103,6 +103,10 @@ def batch_labels(torch, labels, idx, F):
 
 
 def train(args):
+    """Trains on ensembles first .. first + ensembles - 1.  With --state the
+    parameters, Adam moments, step count and the next ensemble are kept in an
+    .npz file, so a run stopped by --max-seconds continues where it stopped
+    (the learning-rate schedule runs over the whole planned number of steps)."""
     import torch
     import paper_2511_21647_amd as ulm
     sim = Simulator()
@@ -112,14 +116,26 @@ def train(args):
     params = torch.from_numpy(init).cuda()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
+    step, hist, start = 0, [], 0
+    if args.state and os.path.exists(args.state):
+        st = np.load(args.state)
+        params = torch.from_numpy(st["params"]).cuda()
+        m = torch.from_numpy(st["m"]).cuda()
+        v = torch.from_numpy(st["v"]).cuda()
+        step, start = int(st["step"]), int(st["next"])
+        hist = json.loads(str(st["history"]))
+        log(f"continuing from {args.state}: ensemble {args.first + start}, step {step}")
     prec = ulm.ULM_CNN_BF16
     B = args.batch
     ws = ulm.Workspace(ulm.ulm_cnn_workspace_size(B, nz, nu, prec, True), "cuda")
-    rng = np.random.Generator(np.random.PCG64(args.seed))
-    step, hist = 0, []
+    rng = np.random.Generator(np.random.PCG64(args.seed + start))
     total_steps = args.ensembles * args.passes * (2 * F // B)
     t0 = time.time()
-    for i in range(args.ensembles):
+    done = True
+    for i in range(start, args.ensembles):
+        if args.max_seconds and time.time() - t0 > args.max_seconds:
+            start, done = i, False
+            break
         e = args.first + i
         images, labels, n_mb = sim.ensemble(e)
         losses = []
@@ -139,6 +155,13 @@ def train(args):
                      "loss_last": float(ls[-1]), "loss_mean": float(ls.mean())})
         log(f"ensemble {e} ({n_mb} MBs): loss {ls[0]:.4e} -> {ls[-1]:.4e} "
             f"(mean {ls.mean():.4e}), step {step}, {time.time() - t0:.0f} s")
+    if args.state:
+        np.savez(args.state, params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(),
+                 step=step, next=start if not done else args.ensembles, history=json.dumps(hist))
+    if not done:
+        log(f"stopped after {time.time() - t0:.0f} s at ensemble {args.first + start}; state in "
+            f"{args.state}")
+        return
     out = params.cpu().numpy()
     np.save(args.out, out)
     with open(os.path.splitext(args.out)[0] + "_train.json", "w") as fh:
@@ -251,6 +274,11 @@ def main():
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default="cnn_weights.npy")
     ap.add_argument("--init", default=None, help="weights (.npy) to continue training from")
+    ap.add_argument("--state", default=None,
+                    help=".npz holding parameters, Adam moments and progress (read if present, "
+                         "written at the end or when --max-seconds stops the run)")
+    ap.add_argument("--max-seconds", type=float, default=0.0,
+                    help="stop before the next ensemble once this much time has passed")
     ap.add_argument("--first", type=int, default=TRAIN_SEED0, help="first training ensemble")
     ap.add_argument("--evaluate", default=None, help="weights (.npy) to evaluate instead")
     ap.add_argument("--thresholds", default="0.5",

@@ -83,6 +83,10 @@ __global__ void cnn_prepare_kernel(const float *__restrict__ p, T *__restrict__ 
     wt[(size_t)l * kWl + (c * 9 + (8 - tap)) * kC + o] = v;
 }
 
+// |v| with one fixed rounding sequence (im^2 fused onto the rounded re^2), so
+// every kernel that forms the network input gets the same bits
+__device__ inline float cnn_mag(float2 v) { return sqrtf(fmaf(v.y, v.y, v.x * v.x)); }
+
 // x0[n][i] = |P[n0 + n][i]| / max over that image of |P|   (0 for an all-zero image)
 __global__ __launch_bounds__(256) void cnn_input_kernel(const float2 *__restrict__ P,
                                                         const float *__restrict__ fmax,
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(256) void cnn_input_kernel(const float2 *__restrict
     if (i >= npix) return;
     const float2 v = P[(size_t)(n0 + n) * npix + i];
     const float m = fmax[n0 + n];
-    x0[(size_t)n * npix + i] = m > 0.f ? sqrtf(v.x * v.x + v.y * v.y) / m : 0.f;
+    x0[(size_t)n * npix + i] = m > 0.f ? cnn_mag(v) / m : 0.f;
 }
 
 // ----------------------------------------------------------------- layer 0 (1 -> 32)
@@ -264,6 +268,126 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const T *__restrict__ in,
     }
 }
 
+// BF16 forward form of the 32 -> 32 convolution with taller tiles and the next
+// tile's loads in flight: 8 x 32 output pixels per tile (two rows per wave, the
+// B operands of a tap shared by both), the input tile (10 x 34 pixels) staged
+// in one of two LDS buffers while the other is read, the next tile's channel
+// vectors held in registers during the MFMAs.  Two barriers per tile.
+constexpr int kCvRows = 8;
+
+__global__ __launch_bounds__(256, 2) void cnn_conv_fwd_bf16_kernel(const bf16 *__restrict__ in,
+                                                                   const bf16 *__restrict__ w,
+                                                                   const float *__restrict__ bias,
+                                                                   bf16 *__restrict__ out, int H, int W,
+                                                                   int B)
+{
+    constexpr int PS = Lds<bf16>::px, WS = Lds<bf16>::w, TC = kTileCols + 2, TR = kCvRows + 2;
+    constexpr int ES = kEpiStride<bf16>, VEC = 8;
+    constexpr int NV = TR * TC * 4;                          // 16-byte vectors per input tile
+    constexpr int NQ = (NV + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 tile[2][TR * TC * PS];
+    __shared__ __attribute__((aligned(16))) bf16 wl[kC * WS];
+    static_assert(4 * 2 * kTileCols * ES <= TR * TC * PS, "epilogue fits in a tile buffer");
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int e = t; e < kC * 36; e += 256) {
+        const int o = e / 36, q = e % 36;
+        *reinterpret_cast<uint4 *>(&wl[o * WS + q * 8]) = reinterpret_cast<const uint4 *>(w)[e];
+    }
+    const int tx = cdiv(W, kTileCols), ty = cdiv(H, kCvRows);
+    const long ntiles = (long)tx * ty * B;
+    const int i32 = lane & 31, hk = lane >> 5;
+    const float b = bias[i32];
+    uint4 pre[NQ];
+    auto load = [&](long tl) {
+        const int n = (int)(tl / ((long)tx * ty)), y0 = (int)((tl / tx) % ty) * kCvRows,
+                  x0 = (int)(tl % tx) * kTileCols;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * 256;
+            const int q4 = e & 3, px = (e >> 2) % TC, ry = (e >> 2) / TC;
+            const int yy = y0 + ry - 1, xx = x0 + px - 1;
+            pre[q] = make_uint4(0, 0, 0, 0);
+            if (e < NV && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                pre[q] = reinterpret_cast<const uint4 *>(in + (((size_t)n * H + yy) * W + xx) * kC)[q4];
+        }
+    };
+    auto put = [&](int bufi) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * 256;
+            if (e < NV) {
+                const int q4 = e & 3, px = (e >> 2) % TC, ry = (e >> 2) / TC;
+                *reinterpret_cast<uint4 *>(&tile[bufi][(ry * TC + px) * PS + q4 * 8]) = pre[q];
+            }
+        }
+    };
+    long tl = blockIdx.x;
+    if (tl < ntiles) {
+        load(tl);
+        put(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (; tl < ntiles; tl += gridDim.x) {
+        const int n = (int)(tl / ((long)tx * ty)), y0 = (int)((tl / tx) % ty) * kCvRows,
+                  x0 = (int)(tl % tx) * kTileCols;
+        const long nxt = tl + gridDim.x;
+        if (nxt < ntiles) load(nxt);
+        // rows wave and wave + 4 of the tile; two accumulation chains per row
+        f32x16 acc[2][2] = {{{}, {}}, {{}, {}}};
+        const bf16 *tb = tile[cur];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            const bf16 *brow = &wl[i32 * WS + tap * kC];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(brow + h * 16 + hk * 8);
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const bf16 *arow = &tb[((wave + 4 * r + dy) * TC + i32 + dx) * PS];
+                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(arow + h * 16 + hk * 8);
+                    acc[r][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[r][h], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();          // every wave is done reading tile[cur]
+        // lane holds D[8 (q / 4) + 4 hk + q % 4][i32]: pixel of the row, output channel i32;
+        // tile[cur] is reused to transpose the results
+        bf16 *epw = tile[cur] + wave * 2 * kTileCols * ES;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const f32x16 a = acc[r][0] + acc[r][1];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int pr = 8 * (q >> 2) + 4 * hk + (q & 3);
+                epw[(r * kTileCols + pr) * ES + i32] = fromf<bf16>(fmaxf(a[q] + b, 0.f));
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);       // this wave's LDS writes have landed
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = y0 + wave + 4 * r;
+            if (y >= H) continue;
+            constexpr int NR = kTileCols * kC / VEC;       // 16-byte vectors per output row
+#pragma unroll
+            for (int c = lane; c < NR; c += 64) {
+                const int pr = c / (kC / VEC), g = c % (kC / VEC);
+                const int x = x0 + pr;
+                if (x < W) {
+                    const size_t at = (((size_t)n * H + y) * W + x) * kC + g * VEC;
+                    *reinterpret_cast<uint4 *>(out + at) =
+                        *reinterpret_cast<const uint4 *>(&epw[(r * kTileCols + pr) * ES + g * VEC]);
+                }
+            }
+        }
+        if (nxt < ntiles) put(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
 // ----------------------------------------------------------------- head
 // Stage the head weights (T, padded rows) and biases in LDS.
 template <typename T>
@@ -343,103 +467,108 @@ __global__ void cnn_d2s_kernel(const float *__restrict__ logits, float *__restri
 }
 
 // ----------------------------------------------------------------- fused head + decode
-// One work-group per (image, coarse row y).  For each 32-column chunk the head
-// runs on coarse rows y-1, y, y+1 and columns x0-1 .. x0+32 (waves 0-2: the
-// three rows, wave 3: the six edge pixels), giving every fine pixel of row y its
-// 8 fine neighbours.  Candidates: heat >= thr, heat above the neighbours earlier
-// in fine raster order and not below the later ones.  Records are compacted in
-// (coarse column, fine row, fine column) order into the row's staging slot.
+// One work-group per (image, band of kHdRows coarse rows).  For each chunk of
+// 32 coarse columns the head runs once on the band's rows and the rows above
+// and below it (coarse rows y0-1 .. y0+kHdRows, columns x0-1 .. x0+32), so every
+// fine pixel of the band has its 8 fine neighbours in LDS.  Candidates: heat >=
+// thr, above the neighbours earlier in fine raster order and not below the
+// later ones.  Each coarse row's records are compacted in (coarse column, fine
+// row, fine column) order into that row's staging slot.
+constexpr int kHdRows = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256, 4) void cnn_head_decode_kernel(
+__global__ __launch_bounds__(256, 2) void cnn_head_decode_kernel(
     const T *__restrict__ a6, const float *__restrict__ p, const float2 *__restrict__ P, float thr,
     int H, int W, int n0, int F, ulm_loc_t *__restrict__ staged, int *__restrict__ row_cnt,
     int row_cap, int *__restrict__ status)
 {
-    constexpr int HC = kTileCols + 2;
+    constexpr int HC = kTileCols + 2, HR = kHdRows + 2, NS = HR * HC;
     __shared__ __attribute__((aligned(16))) T whs[kR2 * Lds<T>::wh];
     __shared__ float bhs[kR2];
-    __shared__ float hs[3][HC][kR2 + 1];       // +1: the decode's 64 lanes (8 columns x 8 fine rows) hit 64 banks
-    __shared__ int wave_tot[4];
-    __shared__ int base_s;
+    __shared__ float hs[HR][HC][kR2 + 1];       // +1: the decode's 64 lanes (8 columns x 8 fine rows) hit 64 banks
+    __shared__ int wave_tot[kHdRows][4];
+    __shared__ int base_s[kHdRows];
     stage_head<T>(p, whs, bhs);
-    if (threadIdx.x == 0) base_s = 0;
+    if (threadIdx.x < kHdRows) base_s[threadIdx.x] = 0;
     __syncthreads();
-    const int y = blockIdx.x, n = blockIdx.y, img = n0 + n;
+    const int y0 = blockIdx.x * kHdRows, n = blockIdx.y, img = n0 + n;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, i32 = lane & 31, hk = lane >> 5;
     const T *act = a6 + (size_t)n * H * W * kC;
-    ulm_loc_t *out = staged + ((size_t)img * H + y) * row_cap;
+    const int cx = t >> 3, i = t & 7;           // decode: coarse column, fine row
     for (int x0 = 0; x0 < W; x0 += kTileCols) {
-        // the pixel this lane supplies: row r (0..2 = y-1..y+1), chunk column cc (0..33)
-        int r, cc;
-        if (wave < 3) { r = wave; cc = 1 + i32; }
-        else if (i32 < 6) { r = i32 >> 1; cc = (i32 & 1) ? HC - 1 : 0; }
-        else { r = -1; cc = 0; }
-        const int yy = y + r - 1, xx = x0 + cc - 1;
-        const bool ok = r >= 0 && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        f32x16 acc[2];
-        head_group<T>(act, ok ? (long)yy * W + xx : -1L, whs, acc);
-        // row q of the 32 x 64 product belongs to the pixel of lane 8(q/4) + 4hk + q%4
+        // head on slot s = row r * HC + column c of the block, 32 slots per wave task
+        for (int gi = wave; gi * 32 < NS; gi += 4) {
+            const int s = gi * 32 + i32;
+            const int r = s / HC, c = s % HC;
+            const int yy = y0 + r - 1, xx = x0 + c - 1;
+            const bool ok = s < NS && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            f32x16 acc[2];
+            head_group<T>(act, ok ? (long)yy * W + xx : -1L, whs, acc);
+            // row q of the 32 x 64 product belongs to slot gi * 32 + 8(q/4) + 4hk + q%4
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int src = 8 * (q >> 2) + 4 * hk + (q & 3);
-            if (wave == 3 && src >= 6) continue;
-            const int rr = wave < 3 ? wave : src >> 1;
-            const int c2 = wave < 3 ? 1 + src : ((src & 1) ? HC - 1 : 0);
-            const int yq = y + rr - 1, xq = x0 + c2 - 1;
-            const bool okq = yq >= 0 && yq < H && xq >= 0 && xq < W;
+            for (int q = 0; q < 16; ++q) {
+                const int s2 = gi * 32 + 8 * (q >> 2) + 4 * hk + (q & 3);
+                if (s2 >= NS) continue;
+                const int r2 = s2 / HC, c2 = s2 % HC;
+                const int yq = y0 + r2 - 1, xq = x0 + c2 - 1;
+                const bool okq = yq >= 0 && yq < H && xq >= 0 && xq < W;
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const int k = nb * 32 + i32;
-                hs[rr][c2][k] = okq ? acc[nb][q] + bhs[k] : -INFINITY;
-            }
-        }
-        __syncthreads();
-        // decode the 32 x 64 fine pixels of row y in this chunk: thread t tests the
-        // 8 fine pixels (coarse column t / 8, fine row t % 8), so thread order is
-        // the raster order of the chunk; a wave scan and the wave totals give
-        // every candidate its slot
-        const int cx = t >> 3, i = t & 7, x = x0 + cx;
-        unsigned bits = 0;
-        float vals[kR];
-        if (x < W) {
-            // fine rows i-1..i+1 and fine columns -1..8 around this thread's 8 pixels,
-            // read once (fine offsets are taken within coarse rows y-1..y+1 and
-            // columns x-1..x+1 of the chunk)
-            float nv[3][kR + 2];
-#pragma unroll
-            for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-                for (int c = 0; c < kR + 2; ++c) {
-                    const int fi = 7 + i + dz, fj = 7 + c;
-                    nv[dz][c] = hs[fi >> 3][cx + (fj >> 3)][(fi & 7) * kR + (fj & 7)];
+                for (int nb = 0; nb < 2; ++nb) {
+                    const int k = nb * 32 + i32;
+                    hs[r2][c2][k] = okq ? acc[nb][q] + bhs[k] : -INFINITY;
                 }
-#pragma unroll
-            for (int j = 0; j < kR; ++j) {
-                const float v = nv[1][j + 1];
-                vals[j] = v;
-                const bool cand = v >= thr && v > nv[0][j] && v > nv[0][j + 1] && v > nv[0][j + 2] &&
-                                  v > nv[1][j] && v >= nv[1][j + 2] && v >= nv[2][j] &&
-                                  v >= nv[2][j + 1] && v >= nv[2][j + 2];
-                bits |= cand ? 1u << j : 0u;
             }
         }
-        const int cnt = __popc(bits);
-        int incl = cnt;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int v = __shfl_up(incl, d);
-            if (lane >= d) incl += v;
-        }
-        if (lane == 63) wave_tot[wave] = incl;
         __syncthreads();
-        int off = base_s + incl - cnt;
-        for (int q = 0; q < wave; ++q) off += wave_tot[q];
-        if (bits) {
-            const float2 pv = P[((size_t)img * H + y) * W + x];
-            const float inten = sqrtf(pv.x * pv.x + pv.y * pv.y);
+        // decode the band's rows: thread t tests the 8 fine pixels (coarse column
+        // t / 8, fine row t % 8) of each row, so thread order is the raster order
+        // of the chunk within a row; a wave scan and the wave totals give every
+        // candidate its slot
+        const int x = x0 + cx;
+        unsigned bits[kHdRows];
+        int incl[kHdRows], cnt[kHdRows];
 #pragma unroll
+        for (int ry = 0; ry < kHdRows; ++ry) {
+            bits[ry] = 0;
+            if (x < W && y0 + ry < H) {
+                float nv[3][kR + 2];
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                    for (int c = 0; c < kR + 2; ++c) {
+                        const int fi = 7 + i + dz, fj = 7 + c;
+                        nv[dz][c] = hs[ry + (fi >> 3)][cx + (fj >> 3)][(fi & 7) * kR + (fj & 7)];
+                    }
+#pragma unroll
+                for (int j = 0; j < kR; ++j) {
+                    const float v = nv[1][j + 1];
+                    const bool cand = v >= thr && v > nv[0][j] && v > nv[0][j + 1] && v > nv[0][j + 2] &&
+                                      v > nv[1][j] && v >= nv[1][j + 2] && v >= nv[2][j] &&
+                                      v >= nv[2][j + 1] && v >= nv[2][j + 2];
+                    bits[ry] |= cand ? 1u << j : 0u;
+                }
+            }
+            cnt[ry] = __popc(bits[ry]);
+            incl[ry] = cnt[ry];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl[ry], d);
+                if (lane >= d) incl[ry] += v;
+            }
+            if (lane == 63) wave_tot[ry][wave] = incl[ry];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ry = 0; ry < kHdRows; ++ry) {
+            if (!bits[ry]) continue;
+            const int y = y0 + ry;
+            int off = base_s[ry] + incl[ry] - cnt[ry];
+            for (int q = 0; q < wave; ++q) off += wave_tot[ry][q];
+            ulm_loc_t *out = staged + ((size_t)img * H + y) * row_cap;
+            const float2 pv = P[((size_t)img * H + y) * W + x];
+            const float inten = cnn_mag(pv);
             for (int j = 0; j < kR; ++j) {
-                if (!(bits & (1u << j))) continue;
+                if (!(bits[ry] & (1u << j))) continue;
                 if (off < row_cap) {
                     ulm_loc_t rec;
                     rec.plane = img / F;
@@ -448,7 +577,7 @@ __global__ __launch_bounds__(256, 4) void cnn_head_decode_kernel(
                     rec.iu = x;
                     rec.z = ((float)(y * kR + i) + 0.5f) / kR - 0.5f;
                     rec.u = ((float)(x * kR + j) + 0.5f) / kR - 0.5f;
-                    rec.ncc = vals[j];
+                    rec.ncc = hs[ry + 1][cx + 1][i * kR + j];
                     rec.intensity = inten;
                     out[off] = rec;
                 }
@@ -456,12 +585,318 @@ __global__ __launch_bounds__(256, 4) void cnn_head_decode_kernel(
             }
         }
         __syncthreads();       // hs and wave_tot are rewritten by the next chunk
-        if (t == 0) base_s += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+        if (t < kHdRows) base_s[t] += wave_tot[t][0] + wave_tot[t][1] + wave_tot[t][2] + wave_tot[t][3];
         __syncthreads();
     }
-    if (t == 0) {
-        row_cnt[(size_t)img * H + y] = min(base_s, row_cap);
-        if (base_s > row_cap) atomicOr(status, kStatusCnnRow);
+    if (t < kHdRows && y0 + t < H) {
+        row_cnt[(size_t)img * H + y0 + t] = min(base_s[t], row_cap);
+        if (base_s[t] > row_cap) atomicOr(status, kStatusCnnRow);
+    }
+}
+
+// ----------------------------------------------------------------- fused BF16 inference
+// The whole BF16 inference of one horizontal strip of one image in one
+// work-group: the input envelope, the six convolutions, the head and the
+// decode run as a pipeline over the image columns, every stage one column of
+// the strip per step, with each layer's recent columns held in LDS rings.  No
+// activation reaches HBM; the only global traffic is the plane (read once) and
+// the records.
+//
+// Strip: SH <= kFuseStrip decode rows ys .. ys + SH - 1.  A stage's column
+// covers the rows its consumers need: layer j (j = 0 input, 1..6 conv0..conv5
+// outputs, 7 heat) holds rows ys - e_j .. ys + SH + e_j - 1 with e = 7 - j for
+// j <= 6 and e = 1 for the heat, so a 3x3 consumer reads producer indices
+// c, c + 1, c + 2 for its index c.  Rows outside the image are stored as zero
+// (the zero padding of every convolution), heat outside the image as -inf.
+//
+// Step it: stage j handles column it - lag_j, lags 0 (input), 2, 4, .., 12
+// (conv0 .. conv5), 13 (head), 15 (decode).  A 3x3 consumer reads its
+// producer's columns x - 1 .. x + 1, all written in earlier steps, so one
+// barrier per step orders everything; 4-slot rings (2 for the head's input)
+// are never overwritten while read.  Taps whose column lies outside the image
+// are skipped, which adds exactly the zeros the padding would.
+//
+// The arithmetic is the same as the layer-by-layer form (cnn_conv0_kernel,
+// cnn_conv_kernel, cnn_head_decode_kernel): the same FMA order in conv0, the
+// same MFMA sequence per output (taps in order, two channel-half chains summed
+// at the end), the same epilogues and decode rule, so the records are
+// identical.  The MFMAs run transposed (weights as the A operand, activations
+// as B): each lane then ends with 16 channels of one pixel, written to LDS as
+// four 8-byte runs.
+//
+// Waves (12): 0..9 conv1..conv5 (layer 1 + w/2, rows 32 (w & 1) ..), 0..6
+// also the decode (8 lanes per row, one per fine row); 10..11 conv0 and the
+// head, 11 also the input.  Activation slots hold 66 pixels x 32 channels, the
+// 16-byte channel groups swizzled by (pixel / 2) mod 4 so 8 consecutive pixels
+// read one group from 8 distinct bank groups.
+constexpr int kFuseStrip = 50;                  // decode rows per strip at most
+constexpr int kFuseSlot = 66;                   // pixels per activation slot
+constexpr int kFuseHeatRows = kFuseStrip + 2;
+constexpr int kFuseHeatStride = kR2 + 1;        // decode lanes (8 rows x 8 fine rows) hit 64 banks
+constexpr int kFuseInRows = kFuseStrip + 14;
+constexpr int kFuseLagHead = 13, kFuseLagDecode = 15;
+constexpr int kFuseThreads = 768;
+
+__device__ inline int fuse_swz(int px) { return (px >> 1) & 3; }
+
+__global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
+    const float *__restrict__ p, const bf16 *__restrict__ wm, const float2 *__restrict__ P,
+    const float *__restrict__ fmaxv, float thr, int H, int W, int F, int n_strips, int SH,
+    ulm_loc_t *__restrict__ staged, int *__restrict__ row_cnt, int row_cap, int *__restrict__ status)
+{
+    __shared__ __attribute__((aligned(16))) bf16 ring[5][4][kFuseSlot * kC];    // conv0 .. conv4 outputs
+    __shared__ __attribute__((aligned(16))) bf16 ring6[2][kFuseSlot * kC];      // conv5 output
+    __shared__ float heat[4][kFuseHeatRows * kFuseHeatStride];
+    __shared__ float x0r[4][kFuseInRows];
+    __shared__ float inten[16][kFuseStrip];
+    __shared__ float w0s[kW0 + kB0];
+    __shared__ __attribute__((aligned(16))) bf16 whs[kR2 * Lds<bf16>::wh];
+    __shared__ __attribute__((aligned(16))) float bhs[kR2];
+    __shared__ __attribute__((aligned(16))) float bcs[kL - 1][kC];
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, i32 = lane & 31, hk = lane >> 5;
+    const int img = blockIdx.x / n_strips, ys = (blockIdx.x % n_strips) * SH;
+    for (int e = t; e < kW0 + kB0; e += kFuseThreads) w0s[e] = p[e];
+    for (int e = t; e < (kL - 1) * kC; e += kFuseThreads) bcs[e / kC][e % kC] = p[off_b(1 + e / kC) + e % kC];
+    stage_head<bf16>(p, whs, bhs);
+    const int n_it = W + kFuseLagDecode;
+
+    // Two role loops, one barrier per step in each, so the conv weights held
+    // by waves 0..9 are not live in the code of waves 10..11.
+    if (wave < 10) {
+        // ---- waves 0..9: conv1 .. conv5 (layer 1 + w/2, output rows 32 (w & 1) ..),
+        // waves 0..6 also the decode
+        const int layer = 1 + (wave >> 1), c0 = 32 * (wave & 1);
+        bf16x8 wr[9][2];                             // A operand: output channel i32
+        {
+            const bf16 *wl = wm + (size_t)(layer - 1) * kWl + (size_t)i32 * 9 * kC;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    wr[tap][h] = *reinterpret_cast<const bf16x8 *>(wl + tap * kC + 16 * h + 8 * hk);
+        }
+        const bf16 *src = &ring[layer - 1][0][0];
+        bf16 *dst0 = layer < 5 ? &ring[layer][0][0] : &ring6[0][0];
+        const int dst_mask = layer < 5 ? 3 : 1, e_out = 6 - layer;
+        const float *bl = bcs[layer - 1];
+        // decode lanes: row ys + (t >> 3), fine row t & 7; records of the row so far
+        const int dy_rel = t >> 3, dfi = t & 7, dy = ys + dy_rel;
+        const bool dec_ok = wave < 7 && dy_rel < SH && dy < H;
+        int base = 0;
+        __syncthreads();
+        for (int it = 0; it < n_it; ++it) {
+            const int x = it - 2 * (layer + 1);
+            if (x >= 0 && x < W) {
+                f32x16 acc[2] = {{}, {}};
+                // taps outside the image add zeros: their operands are read as zero
+                // and the MFMA still runs; the next tap's operands are read while
+                // this tap's MFMAs run
+                bf16x8 bv[2][2];
+                auto fetch = [&](int tap, int slot) {
+                    const int dyy = tap / 3, dx = tap % 3, col = x + dx - 1;
+                    const int pp = c0 + i32 + dyy;
+                    const bf16 *pix = src + ((col & 3) * kFuseSlot + pp) * kC;
+                    const bool in = col >= 0 && col < W;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        bv[slot][h] = *reinterpret_cast<const bf16x8 *>(pix + ((2 * h + hk) ^ fuse_swz(pp)) * 8);
+                        if (!in) bv[slot][h] = bf16x8{};
+                    }
+                };
+                fetch(0, 0);
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    if (tap + 1 < 9) fetch(tap + 1, (tap + 1) & 1);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[tap][h], bv[tap & 1][h], acc[h], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const f32x16 a = acc[0] + acc[1];
+                // lane holds output channels 8 (q / 4) + 4 hk + q % 4 of index c
+                const int c = c0 + i32, row = ys - e_out + c;
+                const bool ok = c < SH + 2 * e_out && row >= 0 && row < H;
+                bf16 *dst = dst0 + ((x & dst_mask) * kFuseSlot + c) * kC;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float4 b4 = *reinterpret_cast<const float4 *>(&bl[8 * r + 4 * hk]);
+                    const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+                    bf16 v4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        v4[j] = fromf<bf16>(ok ? fmaxf(a[4 * r + j] + bb[j], 0.f) : 0.f);
+                    *reinterpret_cast<uint2 *>(dst + (r ^ fuse_swz(c)) * 8 + 4 * hk) =
+                        *reinterpret_cast<const uint2 *>(v4);
+                }
+            }
+            // ---- decode: 3x3 local maxima of the fine heatmap at or above thr,
+            // records in (coarse column, fine row, fine column) order within each row
+            const int xd = it - kFuseLagDecode;
+            if (wave < 7 && xd >= 0 && xd < W) {
+                unsigned bits = 0;
+                if (dec_ok) {
+                    // neighbours earlier in raster order must be below the pixel,
+                    // later ones not above it
+                    auto fine_row = [&](int dz, float (&r)[kR + 2]) {
+                        const int fi = 7 + dfi + dz;
+                        const float *hr = &heat[0][(dy_rel + (fi >> 3)) * kFuseHeatStride + (fi & 7) * kR];
+#pragma unroll
+                        for (int cq = 0; cq < kR + 2; ++cq) {
+                            const int fj = 7 + cq, col = xd - 1 + (fj >> 3);
+                            r[cq] = (col >= 0 && col < W)
+                                        ? hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)]
+                                        : -INFINITY;
+                        }
+                    };
+                    float v[kR], r[kR + 2];
+                    float r0[kR + 2], r2[kR + 2];
+                    fine_row(1, r);
+                    fine_row(0, r0);
+                    fine_row(2, r2);
+#pragma unroll
+                    for (int j = 0; j < kR; ++j) {
+                        v[j] = r[j + 1];
+                        const bool cand = v[j] >= thr && v[j] > r0[j] && v[j] > r0[j + 1] && v[j] > r0[j + 2] &&
+                                          v[j] > r[j] && v[j] >= r[j + 2] && v[j] >= r2[j] &&
+                                          v[j] >= r2[j + 1] && v[j] >= r2[j + 2];
+                        bits |= cand ? 1u << j : 0u;
+                    }
+                }
+                // offsets within the row's 8 lanes (fine rows in order)
+                const int cnt = __popc(bits);
+                int incl = cnt;
+#pragma unroll
+                for (int d = 1; d < 8; d <<= 1) {
+                    const int u = __shfl_up(incl, d, 8);
+                    if (dfi >= d) incl += u;
+                }
+                const int total = __shfl(incl, (lane & ~7) | 7);
+                if (bits) {
+                    int off = base + incl - cnt;
+                    ulm_loc_t *out = staged + ((size_t)img * H + dy) * row_cap;
+                    const float iv = inten[xd & 15][dy_rel];
+                    const float *hc = &heat[xd & 3][(dy_rel + 1) * kFuseHeatStride + dfi * kR];
+                    for (int j = 0; j < kR; ++j) {
+                        if (!(bits & (1u << j))) continue;
+                        if (off < row_cap) {
+                            ulm_loc_t rec;
+                            rec.plane = img / F;
+                            rec.frame = img % F;
+                            rec.iz = dy;
+                            rec.iu = xd;
+                            rec.z = ((float)(dy * kR + dfi) + 0.5f) / kR - 0.5f;
+                            rec.u = ((float)(xd * kR + j) + 0.5f) / kR - 0.5f;
+                            rec.ncc = hc[j];
+                            rec.intensity = iv;
+                            out[off] = rec;
+                        }
+                        ++off;
+                    }
+                }
+                base += total;
+            }
+            __syncthreads();
+        }
+        if (dec_ok && dfi == 0) {
+            row_cnt[(size_t)img * H + dy] = min(base, row_cap);
+            if (base > row_cap) atomicOr(status, kStatusCnnRow);
+        }
+    } else {
+        // ---- waves 10..11: the input (wave 11), conv0 and the head
+        const int tau = t - 640;                     // 0 .. 127
+        const float m = fmaxv[img];
+        const int in_row = ys - 7 + lane;
+        const bool in_ok = wave == 11 && lane < SH + 14 && in_row >= 0 && in_row < H;
+        const float2 *prow = P + ((size_t)img * H + (in_ok ? in_row : 0)) * W;
+        auto in_load = [&](int x) { return in_ok && x < W ? prow[x] : make_float2(0.f, 0.f); };
+        // the next two columns in flight
+        float2 pf0 = in_load(0), pf1 = in_load(1);
+        const int c = 32 * (wave - 10) + i32;       // head: heat index of this lane
+        __syncthreads();
+        // conv0 items of this thread all have channel group tau & 3: its 8
+        // channels' weights and biases stay in registers
+        const int cc = tau & 3;
+        float w0r[8][9], b0r[8];
+#pragma unroll
+        for (int o8 = 0; o8 < 8; ++o8) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) w0r[o8][k] = w0s[(8 * cc + o8) * 9 + k];
+            b0r[o8] = w0s[kW0 + 8 * cc + o8];
+        }
+        for (int it = 0; it < n_it; ++it) {
+            // ---- input: x0 = |P| / frame max (0 outside the image), |P| kept for the records
+            if (wave == 11 && it < W) {
+                const float2 v = pf0;
+                pf0 = pf1;
+                pf1 = in_load(it + 2);
+                if (lane < SH + 14) {
+                    const float mag = cnn_mag(v);
+                    x0r[it & 3][lane] = m > 0.f ? mag / m : 0.f;
+                    if (lane >= 7 && lane < 7 + SH) inten[it & 15][lane - 7] = mag;
+                }
+            }
+            // ---- conv0 (1 -> 32): item = (output index, 8-channel group)
+            const int x = it - 2;
+            if (x >= 0 && x < W) {
+                for (int item = tau; item < (SH + 12) * 4; item += 128) {
+                    const int pi = item >> 2;
+                    float in[9];
+#pragma unroll
+                    for (int dyy = 0; dyy < 3; ++dyy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) {
+                            const int col = x + dx - 1;
+                            in[dyy * 3 + dx] = (col >= 0 && col < W) ? x0r[col & 3][pi + dyy] : 0.f;
+                        }
+                    const int row = ys - 6 + pi;
+                    const bool ok = row >= 0 && row < H;
+                    bf16 res[8];
+#pragma unroll
+                    for (int o8 = 0; o8 < 8; ++o8) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) s = fmaf(w0r[o8][k], in[k], s);
+                        res[o8] = fromf<bf16>(ok ? fmaxf(s + b0r[o8], 0.f) : 0.f);
+                    }
+                    *reinterpret_cast<uint4 *>(&ring[0][x & 3][(pi * 4 + (cc ^ fuse_swz(pi))) * 8]) =
+                        *reinterpret_cast<const uint4 *>(res);
+                }
+            }
+            // ---- head (1x1, 32 -> 64) on conv5's column: 32 rows x 64 outputs per wave
+            const int xh = it - kFuseLagHead;
+            if (xh >= 0 && xh < W) {
+                f32x16 acc[2] = {{}, {}};
+                const bf16 *pix = &ring6[xh & 1][c * kC];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(pix + ((2 * h + hk) ^ fuse_swz(c)) * 8);
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb) {
+                        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+                            whs + (nb * 32 + i32) * Lds<bf16>::wh + h * 16 + hk * 8);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[nb], 0, 0, 0);
+                    }
+                }
+                const int row = ys - 1 + c;
+                const bool ok = row >= 0 && row < H;
+                if (c < SH + 2) {
+                    float *hrow = &heat[xh & 3][c * kFuseHeatStride];
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int k = nb * 32 + 8 * r + 4 * hk;
+                            const float4 b4 = *reinterpret_cast<const float4 *>(&bhs[k]);
+                            hrow[k + 0] = ok ? acc[nb][4 * r + 0] + b4.x : -INFINITY;
+                            hrow[k + 1] = ok ? acc[nb][4 * r + 1] + b4.y : -INFINITY;
+                            hrow[k + 2] = ok ? acc[nb][4 * r + 2] + b4.z : -INFINITY;
+                            hrow[k + 3] = ok ? acc[nb][4 * r + 3] + b4.w : -INFINITY;
+                        }
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -787,6 +1222,11 @@ static unsigned conv_grid(int B, int H, int W) {
     return (unsigned)std::min(tiles, 256L * 8);
 }
 
+static unsigned conv_fwd_grid(int B, int H, int W) {
+    const long tiles = (long)cdiv(W, kTileCols) * cdiv(H, kCvRows) * B;
+    return (unsigned)std::min(tiles, 256L * 4);
+}
+
 template <typename T>
 static hipError_t run_forward(const float *params, const float *x0, T *const *act, int n_act,
                               T *wm, T *wt, int B, int H, int W, hipStream_t st, int *last)
@@ -800,9 +1240,14 @@ static hipError_t run_forward(const float *params, const float *x0, T *const *ac
     int cur = 0;
     for (int l = 1; l < kL; ++l) {
         const int nxt = n_act == kL ? l : cur ^ 1;
-        hipLaunchKernelGGL((cnn_conv_kernel<T, false>), grid, dim3(256), 0, st, act[cur],
-                           wm + (size_t)(l - 1) * kWl, params + off_b(l), (const T *)nullptr,
-                           act[nxt], H, W, B);
+        if constexpr (sizeof(T) == 2)
+            hipLaunchKernelGGL(cnn_conv_fwd_bf16_kernel, dim3(conv_fwd_grid(B, H, W)), dim3(256), 0, st,
+                               act[cur], wm + (size_t)(l - 1) * kWl, params + off_b(l), act[nxt], H, W,
+                               B);
+        else
+            hipLaunchKernelGGL((cnn_conv_kernel<T, false>), grid, dim3(256), 0, st, act[cur],
+                               wm + (size_t)(l - 1) * kWl, params + off_b(l), (const T *)nullptr,
+                               act[nxt], H, W, B);
         cur = nxt;
     }
     *last = cur;
@@ -940,6 +1385,18 @@ static hipError_t localize_t(const float *params, const float2 *P, const float *
     ulm_loc_t *staged = (ulm_loc_t *)(cws + L.staged);
     int *cnt = (int *)(cws + L.cnt), *off = (int *)(cws + L.off);
     hipLaunchKernelGGL(cnn_status_clear_kernel, dim3(1), dim3(64), 0, st, status, kStatusCnnRow);
+    if constexpr (sizeof(T) == 2) {
+        // BF16: the fused strip pipeline over every image at once
+        hipLaunchKernelGGL(cnn_prepare_kernel<T>, dim3(cdiv((kL - 1) * kWl, 256)), dim3(256), 0, st,
+                           params, (T *)(cws + L.wm), (T *)(cws + L.wt));
+        const int n_strips = cdiv(H, kFuseStrip), SH = cdiv(H, n_strips);
+        hipLaunchKernelGGL(cnn_localize_fused_kernel, dim3((unsigned)((long)n_img * n_strips)),
+                           dim3(kFuseThreads), 0, st, params, (const bf16 *)(cws + L.wm), P, fmax, thr,
+                           H, W, F, n_strips, SH, staged, cnt, L.row_cap, status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_compact(cnt, off, n_img * H, count, staged, L.row_cap, locs, capacity, st);
+    }
     for (int n0 = 0; n0 < n_img; n0 += batch) {
         const int nb = std::min(batch, n_img - n0);
         hipError_t e = cnn_images(P, fmax, x0, H * W, n0, nb, st);
@@ -948,7 +1405,7 @@ static hipError_t localize_t(const float *params, const float2 *P, const float *
         if ((e = run_forward<T>(params, x0, act, 2, (T *)(cws + L.wm), (T *)(cws + L.wt), nb, H, W,
                                 st, &last)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(cnn_head_decode_kernel<T>, dim3(H, nb), dim3(256), 0, st, act[last],
+        hipLaunchKernelGGL(cnn_head_decode_kernel<T>, dim3(cdiv(H, kHdRows), nb), dim3(256), 0, st, act[last],
                            params, P, thr, H, W, n0, F, staged, cnt, L.row_cap, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

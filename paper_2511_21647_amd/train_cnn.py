@@ -173,51 +173,93 @@ def train(args):
 
 def match(det, ref, radius=0.5):
     """One-to-one matches of det [n][2] to ref [m][2] within `radius`, nearest
-    pairs first.  Returns (pairs det_i, ref_j)."""
+    pairs first.  Returns (pairs det_i, ref_j).
+
+    Greedy over the candidate pairs sorted by distance, in rounds: a pair that
+    is the nearest remaining one of both its detection and its reference is
+    one the greedy pass accepts, so each round accepts all such pairs and drops
+    every pair that shares an end with them."""
+    det = np.asarray(det, np.float64).reshape(-1, 2)
+    ref = np.asarray(ref, np.float64).reshape(-1, 2)
     if len(det) == 0 or len(ref) == 0:
         return np.zeros(0, int), np.zeros(0, int)
     from scipy.spatial import cKDTree
-    tree = cKDTree(ref)
-    pairs = tree.query_ball_point(det, r=radius)
-    cand = [(np.hypot(*(det[i] - ref[j])), i, j) for i, js in enumerate(pairs) for j in js]
-    cand.sort()
-    used_d, used_r, di, rj = set(), set(), [], []
-    for _, i, j in cand:
-        if i in used_d or j in used_r:
-            continue
-        used_d.add(i)
-        used_r.add(j)
-        di.append(i)
-        rj.append(j)
-    return np.array(di, int), np.array(rj, int)
+    sdm = cKDTree(det).sparse_distance_matrix(cKDTree(ref), radius, output_type="ndarray")
+    # ties broken by (det, ref) index so the result does not depend on the tree
+    o = np.lexsort((sdm["j"], sdm["i"], sdm["v"]))
+    ci, cj = sdm["i"][o].astype(np.int64), sdm["j"][o].astype(np.int64)
+    used_d = np.zeros(len(det), bool)
+    used_r = np.zeros(len(ref), bool)
+    di, rj = [np.zeros(0, np.int64)], [np.zeros(0, np.int64)]
+    while ci.size:
+        first_i = np.zeros(ci.size, bool)
+        first_i[np.unique(ci, return_index=True)[1]] = True
+        first_j = np.zeros(cj.size, bool)
+        first_j[np.unique(cj, return_index=True)[1]] = True
+        acc = first_i & first_j
+        di.append(ci[acc])
+        rj.append(cj[acc])
+        used_d[ci[acc]] = True
+        used_r[cj[acc]] = True
+        keep = ~(used_d[ci] | used_r[cj])
+        ci, cj = ci[keep], cj[keep]
+    return np.concatenate(di), np.concatenate(rj)
 
 
 def per_image(recs, n_img, F):
-    out = [[] for _ in range(n_img)]
-    for r in recs:
-        out[int(r["plane"]) * F + int(r["frame"])].append((float(r["z"]), float(r["u"])))
-    return [np.array(o).reshape(-1, 2) for o in out]
+    """Detections as one (z, u) array per image, image = plane * F + frame."""
+    img = recs["plane"].astype(np.int64) * F + recs["frame"].astype(np.int64)
+    o = np.argsort(img, kind="stable")
+    zu = np.stack([recs["z"][o], recs["u"][o]], axis=1).astype(np.float64)
+    cuts = np.searchsorted(img[o], np.arange(1, n_img))
+    return np.split(zu, cuts)
+
+
+def _stack(images):
+    """All images' points in one array, image n moved by 4096 n px along z (no
+    image is that tall, so points of different images are never within the
+    match radius of each other)."""
+    pts = [np.asarray(p, np.float64).reshape(-1, 2) + [4096.0 * n, 0.0] for n, p in enumerate(images)]
+    return np.concatenate(pts) if pts else np.zeros((0, 2))
 
 
 def score(dets, truth, radius=0.5):
-    n_det = n_ref = n_match = 0
-    sq = []
-    for d, t in zip(dets, truth):
-        i, j = match(d, t, radius)
-        n_det += len(d)
-        n_ref += len(t)
-        n_match += len(i)
-        if len(i):
-            sq.append(np.sum((d[i] - t[j]) ** 2, axis=1))
-    sq = np.concatenate(sq) if sq else np.zeros(0)
-    return {"recall": n_match / max(n_ref, 1), "precision": n_match / max(n_det, 1),
+    d, t = _stack(dets), _stack(truth)
+    i, j = match(d, t, radius)
+    sq = np.sum((d[i] - t[j]) ** 2, axis=1)
+    return {"recall": len(i) / max(len(t), 1), "precision": len(i) / max(len(d), 1),
             "rms_px": float(np.sqrt(sq.mean())) if sq.size else float("nan"),
-            "n_det": n_det, "n_ref": n_ref, "n_match": n_match}
+            "n_det": len(d), "n_ref": len(t), "n_match": len(i)}
 
 
-def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log):
+def _score_ensemble(e, n_mb, ncc, truth, cnn_by_thr):
+    """Scores of one ensemble (CPU only): NCC against the truth; the CNN at each
+    threshold against the truth, against all NCC detections and against NCC's
+    true detections (those matched one-to-one to a true MB within 0.5 px)."""
+    d, t = _stack(ncc), _stack(truth)
+    i, _ = match(d, t)
+    ncc_true = np.zeros(len(d), bool)
+    ncc_true[i] = True
+    counts = np.cumsum([0] + [len(x) for x in ncc])
+    ncc_t = [x[ncc_true[counts[k]:counts[k + 1]]] for k, x in enumerate(ncc)]
+    r = {"ensemble": e, "n_mb": n_mb, "ncc_vs_truth": score(ncc, truth), "cnn": {}}
+    for thr, cnn in cnn_by_thr.items():
+        r["cnn"][thr] = {"vs_truth": score(cnn, truth), "vs_ncc": score(cnn, ncc),
+                         "vs_ncc_true": score(cnn, ncc_t)}
+    return r
+
+
+def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log, workers=4):
     """NCC and CNN on held-out ensembles: each against the truth, and the CNN
-    against NCC as the judge, for every CNN decode threshold given."""
+    against NCC as the judge (all NCC detections, and NCC's true detections),
+    for every CNN decode threshold given.  The matching runs in `workers` CPU
+    processes, forked before the GPU is touched, while the GPU localises the
+    next ensembles."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    pool = ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) if workers > 0 else None
+    if pool is not None:
+        list(pool.map(abs, range(workers)))      # start the workers now
     import torch
     import paper_2511_21647_amd as ulm
     sim = Simulator()
@@ -229,7 +271,7 @@ def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=
     locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
     cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(sim.ctx, 64), "cuda")
-    results = []
+    jobs = []
     for i in range(ensembles):
         e = seed0 + i
         _, labels, n_mb = sim.ensemble(e)
@@ -237,15 +279,22 @@ def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=
         ulm.ncc_localize(sim.ctx, sim.proj, cap, locs, count)
         ulm.ulm_check_status(sim.ctx, count, cap)
         ncc = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
-        r = {"ensemble": e, "n_mb": n_mb, "ncc_vs_truth": score(ncc, truth), "cnn": {}}
+        by_thr = {}
         for thr in thresholds:
             ulm.ulm_cnn_localize(sim.ctx, params, sim.proj, cap, thr, 64, ulm.ULM_CNN_BF16,
                                  locs, count, ws=cws)
             ulm.ulm_check_status(sim.ctx, count, cap)
-            cnn = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
-            r["cnn"][str(thr)] = {"vs_truth": score(cnn, truth), "vs_ncc": score(cnn, ncc)}
+            by_thr[str(thr)] = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
+        args = (e, n_mb, ncc, truth, by_thr)
+        jobs.append(pool.submit(_score_ensemble, *args) if pool else args)
+        log_fn(f"ensemble {e}: {n_mb} MBs localised")
+    results = []
+    for j in jobs:
+        r = j.result() if pool else _score_ensemble(*j)
         results.append(r)
         log_fn(json.dumps(r))
+    if pool is not None:
+        pool.shutdown()
     return results
 
 
@@ -283,10 +332,11 @@ def main():
     ap.add_argument("--evaluate", default=None, help="weights (.npy) to evaluate instead")
     ap.add_argument("--thresholds", default="0.5",
                     help="comma-separated CNN decode thresholds to evaluate")
+    ap.add_argument("--workers", type=int, default=4, help="CPU processes for the matching")
     args = ap.parse_args()
     if args.evaluate:
         thr = tuple(float(x) for x in args.thresholds.split(","))
-        res = evaluate(np.load(args.evaluate), args.ensembles, thr)
+        res = evaluate(np.load(args.evaluate), args.ensembles, thr, workers=args.workers)
         with open(os.path.splitext(args.evaluate)[0] + "_eval.json", "w") as fh:
             json.dump(res, fh, indent=1)
     else:

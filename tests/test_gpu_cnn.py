@@ -210,6 +210,44 @@ def test_cnn_localize_matches_decode(torch, ulm, prec, tiny_cfg, tiny_iq):
         assert abs(float(r["intensity"]) - pz) <= 1e-6 * max(pz, 1e-30)
 
 
+@pytest.mark.parametrize("nz,nu", [(101, 45), (50, 1), (7, 130), (113, 2)])
+def test_cnn_localize_fused_strips(torch, ulm, tiny_cfg, nz, nu):
+    """The BF16 localiser runs every layer of a strip of rows in one work-group,
+    column by column.  On random complex planes of ragged sizes (strips of 34,
+    50, 7 and 38 rows; one, two, 45 and 130 columns) its records equal the
+    decode rule applied to the layer-by-layer BF16 heatmaps, record for record,
+    intensities and all."""
+    from dataclasses import replace
+    cfg = tiny_cfg
+    g = cfg.grid
+    cfg = cfg.with_(grid=replace(g, nz=nz, nu=nu, nv=max(nu, 2), n_blocks=2, v0=g.u0))
+    cfg = cfg.with_(seq=replace(cfg.seq, n_frames=3))
+    ctx = ulm.Context(cfg)
+    rng = np.random.default_rng(nz * 1000 + nu)
+    shape = ctx.proj_shape
+    planes = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    planes[0, 0, 1] *= 0.0                       # an all-zero image: frame maximum 0
+    filt = _dev(torch, planes, torch.complex64)
+    images = ulm.ulm_cnn_images(ctx, filt)
+    params = _dev(torch, ulm.cnn_pack(_params(6)), torch.float32)
+    heat = ulm.ulm_cnn_forward(params, images, ulm.ULM_CNN_BF16).cpu().numpy()
+    F = cfg.seq.n_frames
+    thr, exp = _row_threshold(heat, F, nu)
+    say(f"[cnn fused {nz}x{nu}] threshold {thr:.4f}, {len(exp)} expected")
+    locs, count = ulm.ulm_cnn_localize(ctx, params, filt, capacity=1 << 16, threshold=thr,
+                                       precision=ulm.ULM_CNN_BF16)
+    ulm.ulm_check_status(ctx, count, 1 << 16)
+    got = ulm.locs_to_numpy(locs, count)
+    assert len(got) == len(exp) > 0
+    env = np.abs(planes.reshape(-1, nz, nu))
+    for r, x in zip(got, exp):
+        assert (int(r["plane"]), int(r["frame"]), int(r["iz"]), int(r["iu"])) == x[:4]
+        assert float(r["z"]) == x[6] and float(r["u"]) == x[7]
+        assert np.float32(r["ncc"]) == np.float32(x[8])
+        pz = env[int(r["plane"]) * F + int(r["frame"]), int(r["iz"]), int(r["iu"])]
+        assert abs(float(r["intensity"]) - pz) <= 1e-6 * max(pz, 1e-30)
+
+
 def test_cnn_row_overflow_flag(torch, ulm, tiny_cfg, tiny_iq):
     """A threshold below every heat value floods the per-row staging: the call
     keeps the first peaks of each row and ulm_check_status reports OVERFLOW

@@ -392,7 +392,6 @@ def run_stream(args):
     axial_err = []
     # true MB density on the same 2x grid (fine bin floor((x + 1/2) 2))
     truth = np.zeros((2, 2 * g.nz, 2 * g.nu))
-    dens_oracle = np.zeros((2, 2 * g.nz, 2 * g.nu))
     for e in range(N):
         n_mb = int(round(1000 + 9000 * e / max(N - 1, 1)))
         cfg = cfg_stream(n_mb)
@@ -424,17 +423,6 @@ def run_stream(args):
             ulm.ulm_density_accumulate(ctx, locs, count, cap, dens[form], upsample=2)
             ms[form].append(ev[0].elapsed_time(ev[1]))
             dets[form] += int(count.item())
-        if args.oracle_density:
-            # the oracle's filter and localiser on the library's projections of
-            # this ensemble (outside the timed regions)
-            from oracle import clutter as o_clutter, localize as o_localize, pipeline as o_pipeline
-            ulm.rca_beamform_proj(ctx_p, iq, proj)
-            ph = proj.cpu().numpy().astype(np.complex128)
-            fo, _ = o_clutter.filter_planes(ph, cfg0.svd_cutoff)
-            del ph
-            recs, _, _ = o_localize.localize(fo, cfg0)
-            del fo
-            dens_oracle += o_pipeline.density_map(recs, 2, g.nz, g.nu, upsample=2)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         ev[0].record()
@@ -473,13 +461,6 @@ def run_stream(args):
     out["density_ssim_bf16_cnn_vs_plain"] = [round(ssim(nrm_(db[o]), nrm_(dp[o])), 4) for o in range(2)]
     # each map as a distribution (divided by its total), so the SSIM compares structure
     nrm = lambda m: m / max(float(m.sum()), 1.0)
-    if args.oracle_density:
-        out["density_ssim_vs_oracle"] = {
-            "note": "the oracle's FP64 filter and NCC localiser on the library's projections of "
-                    "every ensemble, accumulated like the library's maps",
-            "plain": [round(ssim(nrm(dp[o]), nrm(dens_oracle[o])), 4) for o in range(2)],
-            "bf16_cnn": [round(ssim(nrm(db[o]), nrm(dens_oracle[o])), 4) for o in range(2)],
-            "plain_counts_equal_fraction": round(float(np.mean(dp == dens_oracle)), 5)}
     out["density_ssim_vs_true_mbs"] = {
         "plain": [round(ssim(nrm(dp[o]), nrm(truth[o])), 4) for o in range(2)],
         "bf16_cnn": [round(ssim(nrm(db[o]), nrm(truth[o])), 4) for o in range(2)]}
@@ -811,10 +792,6 @@ def main():
                     help="write a per-kernel summary (with rooflines) of a rocprofv3 kernel "
                          "trace (rocpd .db or kernel_trace.csv)")
     ap.add_argument("--stream", type=int, default=0, metavar="N")
-    ap.add_argument("--oracle-density", action="store_true",
-                    help="with --stream: also accumulate the density map of the FP64 oracle's "
-                         "filter and localiser on the library's projections, and report the "
-                         "SSIM of each form's map against it (about 7 s of host time per ensemble)")
     ap.add_argument("--inflight", type=int, default=1, metavar="N",
                     help="also time the plain path with N > 1 ensembles in flight on N streams "
                          "(off by default, so every stage-1 launch of the run executes alone "

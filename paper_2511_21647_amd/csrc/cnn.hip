@@ -613,8 +613,9 @@ __global__ __launch_bounds__(256, 2) void cnn_head_decode_kernel(
 // (conv0 .. conv5), 13 (head), 15 (decode).  A 3x3 consumer reads its
 // producer's columns x - 1 .. x + 1, all written in earlier steps, so one
 // barrier per step orders everything; 4-slot rings (2 for the head's input)
-// are never overwritten while read.  Taps whose column lies outside the image
-// are skipped, which adds exactly the zeros the padding would.
+// are never overwritten while read.  Every stage also writes columns -1 and W
+// (zeros; -inf for the heat), so the taps at the image's left and right edges
+// read the zero padding from the rings like any other column.
 //
 // The arithmetic is the same as the layer-by-layer form (cnn_conv0_kernel,
 // cnn_conv_kernel, cnn_head_decode_kernel): the same FMA order in conv0, the
@@ -680,44 +681,57 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
         bf16 *dst0 = layer < 5 ? &ring[layer][0][0] : &ring6[0][0];
         const int dst_mask = layer < 5 ? 3 : 1, e_out = 6 - layer;
         const float *bl = bcs[layer - 1];
+        // per-lane element offsets within a slot: the B operand of row offset dyy
+        // and channel half h, and this lane's four output runs
+        int loff[3][2], eoff[4];
+#pragma unroll
+        for (int dyy = 0; dyy < 3; ++dyy)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int pp = c0 + i32 + dyy;
+                loff[dyy][h] = pp * kC + ((2 * h + hk) ^ fuse_swz(pp)) * 8;
+            }
+        const int c = c0 + i32;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) eoff[r] = c * kC + (r ^ fuse_swz(c)) * 8 + 4 * hk;
         // decode lanes: row ys + (t >> 3), fine row t & 7; records of the row so far
         const int dy_rel = t >> 3, dfi = t & 7, dy = ys + dy_rel;
         const bool dec_ok = wave < 7 && dy_rel < SH && dy < H;
         int base = 0;
         __syncthreads();
-        for (int it = 0; it < n_it; ++it) {
+        for (int it = -1; it < n_it; ++it) {
+            // columns -1 and W are written as zeros, so every read below is unconditional
             const int x = it - 2 * (layer + 1);
-            if (x >= 0 && x < W) {
-                f32x16 acc[2] = {{}, {}};
-                // taps outside the image add zeros: their operands are read as zero
-                // and the MFMA still runs; the next tap's operands are read while
-                // this tap's MFMAs run
-                bf16x8 bv[2][2];
-                auto fetch = [&](int tap, int slot) {
-                    const int dyy = tap / 3, dx = tap % 3, col = x + dx - 1;
-                    const int pp = c0 + i32 + dyy;
-                    const bf16 *pix = src + ((col & 3) * kFuseSlot + pp) * kC;
-                    const bool in = col >= 0 && col < W;
+            if (x >= -1 && x <= W) {
+                f32x16 a = {};
+                if (x >= 0 && x < W) {
+                    f32x16 acc[2] = {{}, {}};
+                    // the next tap's operands are read while this tap's MFMAs run
+                    int sb[3];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        bv[slot][h] = *reinterpret_cast<const bf16x8 *>(pix + ((2 * h + hk) ^ fuse_swz(pp)) * 8);
-                        if (!in) bv[slot][h] = bf16x8{};
+                    for (int dx = 0; dx < 3; ++dx) sb[dx] = ((x + dx - 1) & 3) * kFuseSlot * kC;
+                    bf16x8 bv[2][2];
+                    auto fetch = [&](int tap, int slot) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            bv[slot][h] = *reinterpret_cast<const bf16x8 *>(src + sb[tap % 3] + loff[tap / 3][h]);
+                    };
+                    fetch(0, 0);
+#pragma unroll
+                    for (int tap = 0; tap < 9; ++tap) {
+                        if (tap + 1 < 9) fetch(tap + 1, (tap + 1) & 1);
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[tap][h], bv[tap & 1][h], acc[h], 0,
+                                                                            0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                };
-                fetch(0, 0);
-#pragma unroll
-                for (int tap = 0; tap < 9; ++tap) {
-                    if (tap + 1 < 9) fetch(tap + 1, (tap + 1) & 1);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-                        acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[tap][h], bv[tap & 1][h], acc[h], 0, 0, 0);
-                    __builtin_amdgcn_sched_barrier(0);
+                    a = acc[0] + acc[1];
                 }
-                const f32x16 a = acc[0] + acc[1];
                 // lane holds output channels 8 (q / 4) + 4 hk + q % 4 of index c
-                const int c = c0 + i32, row = ys - e_out + c;
-                const bool ok = c < SH + 2 * e_out && row >= 0 && row < H;
-                bf16 *dst = dst0 + ((x & dst_mask) * kFuseSlot + c) * kC;
+                const int row = ys - e_out + c;
+                const bool ok = x >= 0 && x < W && c < SH + 2 * e_out && row >= 0 && row < H;
+                bf16 *dst = dst0 + (x & dst_mask) * kFuseSlot * kC;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float4 b4 = *reinterpret_cast<const float4 *>(&bl[8 * r + 4 * hk]);
@@ -726,8 +740,7 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         v4[j] = fromf<bf16>(ok ? fmaxf(a[4 * r + j] + bb[j], 0.f) : 0.f);
-                    *reinterpret_cast<uint2 *>(dst + (r ^ fuse_swz(c)) * 8 + 4 * hk) =
-                        *reinterpret_cast<const uint2 *>(v4);
+                    *reinterpret_cast<uint2 *>(dst + eoff[r]) = *reinterpret_cast<const uint2 *>(v4);
                 }
             }
             // ---- decode: 3x3 local maxima of the fine heatmap at or above thr,
@@ -744,9 +757,7 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
 #pragma unroll
                         for (int cq = 0; cq < kR + 2; ++cq) {
                             const int fj = 7 + cq, col = xd - 1 + (fj >> 3);
-                            r[cq] = (col >= 0 && col < W)
-                                        ? hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)]
-                                        : -INFINITY;
+                            r[cq] = hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)];
                         }
                     };
                     float v[kR], r[kR + 2];
@@ -763,15 +774,21 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                         bits |= cand ? 1u << j : 0u;
                     }
                 }
-                // offsets within the row's 8 lanes (fine rows in order)
+                // offsets within the row's 8 lanes (fine rows in order): an inclusive
+                // scan by DPP row shifts, the row's total by quad swaps and the
+                // half-row mirror (no LDS round trips)
                 const int cnt = __popc(bits);
-                int incl = cnt;
-#pragma unroll
-                for (int d = 1; d < 8; d <<= 1) {
-                    const int u = __shfl_up(incl, d, 8);
-                    if (dfi >= d) incl += u;
-                }
-                const int total = __shfl(incl, (lane & ~7) | 7);
+                int incl = cnt, u;
+                u = __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);          // row_shr:1
+                if (dfi >= 1) incl += u;
+                u = __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);          // row_shr:2
+                if (dfi >= 2) incl += u;
+                u = __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);          // row_shr:4
+                if (dfi >= 4) incl += u;
+                int total = cnt;
+                total += __builtin_amdgcn_update_dpp(0, total, 0xb1, 0xf, 0xf, false);     // quad_perm 1,0,3,2
+                total += __builtin_amdgcn_update_dpp(0, total, 0x4e, 0xf, 0xf, false);     // quad_perm 2,3,0,1
+                total += __builtin_amdgcn_update_dpp(0, total, 0x141, 0xf, 0xf, false);    // row_half_mirror
                 if (bits) {
                     int off = base + incl - cnt;
                     ulm_loc_t *out = staged + ((size_t)img * H + dy) * row_cap;
@@ -824,47 +841,57 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
             for (int k = 0; k < 9; ++k) w0r[o8][k] = w0s[(8 * cc + o8) * 9 + k];
             b0r[o8] = w0s[kW0 + 8 * cc + o8];
         }
-        for (int it = 0; it < n_it; ++it) {
-            // ---- input: x0 = |P| / frame max (0 outside the image), |P| kept for the records
-            if (wave == 11 && it < W) {
-                const float2 v = pf0;
-                pf0 = pf1;
-                pf1 = in_load(it + 2);
+        for (int it = -1; it < n_it; ++it) {
+            // ---- input: x0 = |P| / frame max (0 outside the image), |P| kept for the
+            // records; columns -1 and W are zero
+            if (wave == 11 && it >= -1 && it <= W) {
+                float2 v = make_float2(0.f, 0.f);
+                if (it >= 0 && it < W) {
+                    v = pf0;
+                    pf0 = pf1;
+                    pf1 = in_load(it + 2);
+                }
                 if (lane < SH + 14) {
                     const float mag = cnn_mag(v);
                     x0r[it & 3][lane] = m > 0.f ? mag / m : 0.f;
-                    if (lane >= 7 && lane < 7 + SH) inten[it & 15][lane - 7] = mag;
+                    if (lane >= 7 && lane < 7 + SH && it >= 0 && it < W) inten[it & 15][lane - 7] = mag;
                 }
             }
             // ---- conv0 (1 -> 32): item = (output index, 8-channel group)
             const int x = it - 2;
-            if (x >= 0 && x < W) {
+            if (x >= -1 && x <= W) {
+                const bool col_ok = x >= 0 && x < W;
                 for (int item = tau; item < (SH + 12) * 4; item += 128) {
                     const int pi = item >> 2;
-                    float in[9];
-#pragma unroll
-                    for (int dyy = 0; dyy < 3; ++dyy)
-#pragma unroll
-                        for (int dx = 0; dx < 3; ++dx) {
-                            const int col = x + dx - 1;
-                            in[dyy * 3 + dx] = (col >= 0 && col < W) ? x0r[col & 3][pi + dyy] : 0.f;
-                        }
                     const int row = ys - 6 + pi;
-                    const bool ok = row >= 0 && row < H;
-                    bf16 res[8];
+                    const bool ok = col_ok && row >= 0 && row < H;
+                    bf16 res[8] = {};
+                    if (col_ok) {
+                        float in[9];
 #pragma unroll
-                    for (int o8 = 0; o8 < 8; ++o8) {
-                        float s = 0.f;
+                        for (int dyy = 0; dyy < 3; ++dyy)
 #pragma unroll
-                        for (int k = 0; k < 9; ++k) s = fmaf(w0r[o8][k], in[k], s);
-                        res[o8] = fromf<bf16>(ok ? fmaxf(s + b0r[o8], 0.f) : 0.f);
+                            for (int dx = 0; dx < 3; ++dx) in[dyy * 3 + dx] = x0r[(x + dx - 1) & 3][pi + dyy];
+#pragma unroll
+                        for (int o8 = 0; o8 < 8; ++o8) {
+                            float s = 0.f;
+#pragma unroll
+                            for (int k = 0; k < 9; ++k) s = fmaf(w0r[o8][k], in[k], s);
+                            res[o8] = fromf<bf16>(ok ? fmaxf(s + b0r[o8], 0.f) : 0.f);
+                        }
                     }
                     *reinterpret_cast<uint4 *>(&ring[0][x & 3][(pi * 4 + (cc ^ fuse_swz(pi))) * 8]) =
                         *reinterpret_cast<const uint4 *>(res);
                 }
             }
-            // ---- head (1x1, 32 -> 64) on conv5's column: 32 rows x 64 outputs per wave
+            // ---- head (1x1, 32 -> 64) on conv5's column: 32 rows x 64 outputs per
+            // wave; columns -1 and W hold -inf
             const int xh = it - kFuseLagHead;
+            if ((xh == -1 || xh == W) && c < SH + 2) {
+                float *hrow = &heat[xh & 3][c * kFuseHeatStride];
+#pragma unroll
+                for (int k = 0; k < kR2; ++k) hrow[k] = -INFINITY;
+            }
             if (xh >= 0 && xh < W) {
                 f32x16 acc[2] = {{}, {}};
                 const bf16 *pix = &ring6[xh & 1][c * kC];

@@ -724,7 +724,6 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                         for (int h = 0; h < 2; ++h)
                             acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[tap][h], bv[tap & 1][h], acc[h], 0,
                                                                             0, 0);
-                        __builtin_amdgcn_sched_barrier(0);
                     }
                     a = acc[0] + acc[1];
                 }
@@ -760,18 +759,29 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                             r[cq] = hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)];
                         }
                     };
-                    float v[kR], r[kR + 2];
-                    float r0[kR + 2], r2[kR + 2];
-                    fine_row(1, r);
-                    fine_row(0, r0);
-                    fine_row(2, r2);
+                    // the lane's own 8 pixels first: with none at or above thr (most
+                    // of the heatmap) there is no candidate and nothing more to read
+                    float v[kR];
+                    {
+                        const float *hv = &heat[xd & 3][(dy_rel + 1) * kFuseHeatStride + dfi * kR];
 #pragma unroll
-                    for (int j = 0; j < kR; ++j) {
-                        v[j] = r[j + 1];
-                        const bool cand = v[j] >= thr && v[j] > r0[j] && v[j] > r0[j + 1] && v[j] > r0[j + 2] &&
-                                          v[j] > r[j] && v[j] >= r[j + 2] && v[j] >= r2[j] &&
-                                          v[j] >= r2[j + 1] && v[j] >= r2[j + 2];
-                        bits |= cand ? 1u << j : 0u;
+                        for (int j = 0; j < kR; ++j) v[j] = hv[j];
+                    }
+                    bool hot = false;
+#pragma unroll
+                    for (int j = 0; j < kR; ++j) hot |= v[j] >= thr;
+                    if (hot) {
+                        float r[kR + 2], r0[kR + 2], r2[kR + 2];
+                        fine_row(1, r);
+                        fine_row(0, r0);
+                        fine_row(2, r2);
+#pragma unroll
+                        for (int j = 0; j < kR; ++j) {
+                            const bool cand = v[j] >= thr && v[j] > r0[j] && v[j] > r0[j + 1] &&
+                                              v[j] > r0[j + 2] && v[j] > r[j] && v[j] >= r[j + 2] &&
+                                              v[j] >= r2[j] && v[j] >= r2[j + 1] && v[j] >= r2[j + 2];
+                            bits |= cand ? 1u << j : 0u;
+                        }
                     }
                 }
                 // offsets within the row's 8 lanes (fine rows in order): an inclusive

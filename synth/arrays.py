@@ -66,6 +66,30 @@ def gaussian_spots(nz: int, nu: int, n_spots: int, sigma: float, seed: int, spac
     return img, centres
 
 
+def spot_frames(n_frames: int, nz: int, nu: int, per_frame: int, sigma_z: float, sigma_u: float,
+                seed: int, amplitude: float = 10.0, radius: int = 4) -> np.ndarray:
+    """[F][nz][nu] complex64 frames of point-like echoes: per frame, `per_frame`
+    sampled 2D Gaussians (sigmas in pixels) at uniform sub-pixel positions, each
+    with a random phase, added over a (2 radius + 1)^2 patch."""
+    g = rng(seed)
+    out = np.zeros((n_frames, nz, nu), dtype=np.complex128)
+    d = np.arange(-radius, radius + 1)
+    for f in range(n_frames):
+        cz = g.uniform(0, nz, per_frame)
+        cu = g.uniform(0, nu, per_frame)
+        ph = np.exp(2j * np.pi * g.uniform(0, 1, per_frame))
+        iz = np.floor(cz).astype(int)[:, None] + d[None, :]          # [n][2r+1]
+        iu = np.floor(cu).astype(int)[:, None] + d[None, :]
+        wz = np.exp(-(iz - cz[:, None]) ** 2 / (2 * sigma_z ** 2))
+        wu = np.exp(-(iu - cu[:, None]) ** 2 / (2 * sigma_u ** 2))
+        val = amplitude * ph[:, None, None] * wz[:, :, None] * wu[:, None, :]
+        zz = np.broadcast_to(iz[:, :, None], val.shape)
+        uu = np.broadcast_to(iu[:, None, :], val.shape)
+        ok = (zz >= 0) & (zz < nz) & (uu >= 0) & (uu < nu)
+        np.add.at(out[f], (zz[ok], uu[ok]), val[ok])
+    return out.astype(np.complex64)
+
+
 def speckle_field(nz: int, nu: int, seed: int, smooth: float = 1.5) -> np.ndarray:
     """Band-limited complex Gaussian field [nz][nu] (complex128): a speckle
     pattern whose envelope has a correlation length of a few pixels."""

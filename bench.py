@@ -724,6 +724,14 @@ def _kernel_work(name, wgs, gy, gz):
         images = gy
         return ("hbm", images * NPIX_P * 32 * 2, "byte", HBM_PEAK_GBS / 1e3,
                 f"{images} images of BF16 activations read once")
+    if "cnn_localize_fused_kernel" in short:
+        # every image of the ensemble: conv0 (32 x 9), five 32 -> 32 conv3x3
+        # (32 x 288 each) and the head (64 x 32) MACs per pixel; the strips'
+        # halo rows are not counted
+        images = 2 * F_P
+        per_px = 2.0 * (32 * 9 + 5 * 32 * 288 + 64 * 32)
+        return ("mfma", images * NPIX_P * per_px, "flop", BF16_PEAK_TFLOPS,
+                f"{images} images, the whole network per pixel, BF16 MFMA")
     return None
 
 

@@ -746,41 +746,55 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
             // records in (coarse column, fine row, fine column) order within each row
             const int xd = it - kFuseLagDecode;
             if (wave < 7 && xd >= 0 && xd < W) {
-                unsigned bits = 0;
-                if (dec_ok) {
-                    // neighbours earlier in raster order must be below the pixel,
-                    // later ones not above it
-                    auto fine_row = [&](int dz, float (&r)[kR + 2]) {
-                        const int fi = 7 + dfi + dz;
-                        const float *hr = &heat[0][(dy_rel + (fi >> 3)) * kFuseHeatStride + (fi & 7) * kR];
+                // Lane t holds fine row 8 (t / 8) + t % 8 of the strip, so the fine
+                // rows above and below a lane's are its neighbour lanes' own rows:
+                // each lane reads its row (8 pixels of column xd and the edge pixel
+                // of each neighbour column) and takes the other two by DPP wave
+                // shifts; only the first and last lane of a wave read theirs.
+                auto fine_row = [&](int dz, float (&r)[kR + 2]) {
+                    const int fi = 7 + dfi + dz;
+                    const int hrow = min(dy_rel + (fi >> 3), SH + 1);     // lanes past the strip: clamped
+                    const float *hr = &heat[0][hrow * kFuseHeatStride + (fi & 7) * kR];
 #pragma unroll
-                        for (int cq = 0; cq < kR + 2; ++cq) {
-                            const int fj = 7 + cq, col = xd - 1 + (fj >> 3);
-                            r[cq] = hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)];
-                        }
-                    };
-                    // the lane's own 8 pixels first: with none at or above thr (most
-                    // of the heatmap) there is no candidate and nothing more to read
-                    float v[kR];
-                    {
-                        const float *hv = &heat[xd & 3][(dy_rel + 1) * kFuseHeatStride + dfi * kR];
-#pragma unroll
-                        for (int j = 0; j < kR; ++j) v[j] = hv[j];
+                    for (int cq = 0; cq < kR + 2; ++cq) {
+                        const int fj = 7 + cq, col = xd - 1 + (fj >> 3);
+                        r[cq] = hr[(col & 3) * kFuseHeatRows * kFuseHeatStride + (fj & 7)];
                     }
-                    bool hot = false;
+                };
+                float r[kR + 2];
+                fine_row(1, r);
+                bool hot = false;
 #pragma unroll
-                    for (int j = 0; j < kR; ++j) hot |= v[j] >= thr;
-                    if (hot) {
-                        float r[kR + 2], r0[kR + 2], r2[kR + 2];
-                        fine_row(1, r);
-                        fine_row(0, r0);
-                        fine_row(2, r2);
+                for (int j = 0; j < kR; ++j) hot |= r[j + 1] >= thr;
+                unsigned bits = 0;
+                // with none of its pixels at or above thr (most of the heatmap) a
+                // wave has no candidate and stops here
+                if (__ballot(dec_ok && hot)) {
+                    float r0[kR + 2], r2[kR + 2];
+#pragma unroll
+                    for (int cq = 0; cq < kR + 2; ++cq) {
+                        const int x = __float_as_int(r[cq]);
+                        r0[cq] = __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, false));  // wave_shr:1
+                        r2[cq] = __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false));  // wave_shl:1
+                    }
+                    if (lane == 0) fine_row(0, r0);
+                    if (lane == 63) fine_row(2, r2);
+                    if (dec_ok) {
+                        // earlier neighbours in raster order must be below the pixel, later
+                        // ones not above it: against the maxima of each side (the same
+                        // decisions as the nine comparisons for finite heat values)
+                        float p0[kR + 1], p2[kR + 1];
+#pragma unroll
+                        for (int j = 0; j <= kR; ++j) {
+                            p0[j] = fmaxf(r0[j], r0[j + 1]);
+                            p2[j] = fmaxf(r2[j], r2[j + 1]);
+                        }
 #pragma unroll
                         for (int j = 0; j < kR; ++j) {
-                            const bool cand = v[j] >= thr && v[j] > r0[j] && v[j] > r0[j + 1] &&
-                                              v[j] > r0[j + 2] && v[j] > r[j] && v[j] >= r[j + 2] &&
-                                              v[j] >= r2[j] && v[j] >= r2[j + 1] && v[j] >= r2[j + 2];
-                            bits |= cand ? 1u << j : 0u;
+                            const float v = r[j + 1];
+                            const float before = fmaxf(fmaxf(p0[j], r0[j + 2]), r[j]);
+                            const float after = fmaxf(fmaxf(p2[j], r2[j + 2]), r[j + 2]);
+                            bits |= (v >= thr && v > before && v >= after) ? 1u << j : 0u;
                         }
                     }
                 }

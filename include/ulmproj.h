@@ -453,6 +453,18 @@ int32_t ulm_cnn_localize(ulm_ctx_t *ctx, const float *params, const float *filte
                          int32_t capacity, int32_t *count, void *ws, size_t ws_bytes,
                          void *cnn_ws, size_t cnn_ws_bytes, void *stream);
 
+/* The whole path with the learned localiser in place of NCC:
+ * rca_beamform_proj -> svd_clutter_filter -> ulm_cnn_localize.  Arguments as
+ * ulm_reconstruct_ensemble, plus the network's `params`, `threshold`, `batch`,
+ * `precision` and its workspace `cnn_ws` as ulm_cnn_localize; the CNN's
+ * arguments are checked before any work is queued.  Errors: INVALID_ARG, HIP. */
+int32_t ulm_reconstruct_ensemble_cnn(ulm_ctx_t *ctx, const float *iq, float *proj,
+                                     double *eigvals, const float *params, float threshold,
+                                     int32_t batch, int32_t precision, ulm_loc_t *locs,
+                                     int32_t capacity, int32_t *count, void *ws, size_t ws_bytes,
+                                     void *cnn_ws, size_t cnn_ws_bytes, ulm_timing_t *timing,
+                                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

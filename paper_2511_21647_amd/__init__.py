@@ -16,6 +16,7 @@ from ._lib import (ULM_OK, ULM_ERR_INVALID_ARG, ULM_ERR_HIP, ULM_ERR_OVERFLOW, U
                    locs_to_numpy, make_config, ncc_localize, rca_beamform_proj, rca_beamform_stage1,
                    rca_beamform_stage2, rca_beamform_cross, ulm_xdoppler, svd_clutter_filter,
                    ulm_check_status, ulm_density_accumulate, ulm_reconstruct_ensemble,
+                   ulm_reconstruct_ensemble_cnn,
                    ulm_sim_channel_data, LIB_PATH)
 
 __all__ = ["ULM_OK", "ULM_ERR_INVALID_ARG", "ULM_ERR_HIP", "ULM_ERR_OVERFLOW", "ULM_ERR_NUMERIC",
@@ -26,7 +27,7 @@ __all__ = ["ULM_OK", "ULM_ERR_INVALID_ARG", "ULM_ERR_HIP", "ULM_ERR_OVERFLOW", "
            "ULMError", "locs_to_numpy", "make_config", "ncc_localize", "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2",
            "rca_beamform_cross", "ulm_xdoppler",
            "svd_clutter_filter", "ulm_check_status", "ulm_density_accumulate",
-           "ulm_reconstruct_ensemble", "ulm_sim_channel_data", "LIB_PATH",
+           "ulm_reconstruct_ensemble", "ulm_reconstruct_ensemble_cnn", "ulm_sim_channel_data", "LIB_PATH",
            "CNN_LAYOUT", "CNN_THRESHOLD", "CNN_UPSAMPLE", "ULM_CNN_BF16", "ULM_CNN_FP32", "ULM_CNN_PARAMS",
            "Workspace", "cnn_pack", "cnn_unpack", "ulm_cnn_forward", "ulm_cnn_gradients",
            "ulm_cnn_images", "ulm_cnn_localize", "ulm_cnn_localize_workspace_size",

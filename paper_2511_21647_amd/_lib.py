@@ -40,6 +40,7 @@ CNN_LAYOUT = ([("w0", (32, 1, 3, 3)), ("b0", (32,))]
 
 EXPORTS = ("ulm_last_error", "ulm_create", "ulm_destroy", "ulm_workspace_size",
            "rca_beamform_proj", "rca_beamform_stage1", "rca_beamform_stage2", "rca_beamform_cross", "ulm_xdoppler", "svd_clutter_filter", "ncc_localize", "ulm_reconstruct_ensemble",
+           "ulm_reconstruct_ensemble_cnn",
            "ulm_check_status", "ulm_sim_channel_data", "ulm_density_accumulate",
            "ulm_cnn_workspace_size", "ulm_cnn_localize_workspace_size", "ulm_cnn_images",
            "ulm_cnn_forward", "ulm_cnn_gradients", "ulm_cnn_train_step", "ulm_cnn_localize",
@@ -123,6 +124,8 @@ def _load():
                                 i32, vp, vp, sz, vp], i32),
         "ulm_cnn_localize": ([vp, vp, vp, ctypes.c_float, i32, i32, vp, i32, vp, vp, sz, vp, sz,
                               vp], i32),
+        "ulm_reconstruct_ensemble_cnn": ([vp, vp, vp, vp, vp, ctypes.c_float, i32, i32, vp, i32, vp,
+                                          vp, sz, vp, sz, ctypes.POINTER(ULMTiming), vp], i32),
         "ulm_pair_workspace_size": ([vp, i32, ctypes.POINTER(sz)], i32),
         "ulm_pair_planes": ([vp, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
         "ulm_pair_planes_noalloc": ([vp, vp, vp, i32, vp, i32, vp, vp], i32),
@@ -583,6 +586,38 @@ def ulm_cnn_localize(ctx: Context, params, filtered, capacity: int, threshold: f
                                  _ptr(count), ctx.ws_ptr, ctx.ws_bytes, ws.ptr, ws.nbytes,
                                  _stream(stream)))
     return locs, count
+
+
+def ulm_reconstruct_ensemble_cnn(ctx: Context, iq, params, capacity: int,
+                                 threshold: float = CNN_THRESHOLD, batch: int = 64,
+                                 precision: int = ULM_CNN_BF16, proj=None, eigvals=None, locs=None,
+                                 count=None, ws=None, timing: bool = False, stream=None):
+    """The whole path with the CNN localiser.  Returns dict(proj=filtered planes,
+    eigvals, locs, count, timing) as ulm_reconstruct_ensemble."""
+    torch = _torch()
+    _require(iq, torch.complex64, ctx.iq_shape, "iq")
+    _params(params)
+    dev = iq.device
+    if proj is None:
+        proj = torch.empty(ctx.proj_shape, dtype=torch.complex64, device=dev)
+    if eigvals is None:
+        eigvals = torch.empty(ctx.proj_shape[:3], dtype=torch.float64, device=dev)
+    if locs is None:
+        locs = torch.empty((max(capacity, 1), LOC_WORDS), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = _ws(ws, ulm_cnn_localize_workspace_size(ctx, batch, precision), dev)
+    tm = ULMTiming() if timing else None
+    _check(_lib.ulm_reconstruct_ensemble_cnn(ctx.handle, _ptr(iq), _ptr(proj), _ptr(eigvals),
+                                             _ptr(params), ctypes.c_float(threshold), int(batch),
+                                             int(precision), _ptr(locs), int(capacity), _ptr(count),
+                                             ctx.ws_ptr, ctx.ws_bytes, ws.ptr, ws.nbytes,
+                                             ctypes.byref(tm) if tm else None, _stream(stream)))
+    out = {"proj": proj, "eigvals": eigvals, "locs": locs, "count": count}
+    if tm is not None:
+        out["timing"] = {"beamform": tm.ms_beamform, "filter": tm.ms_filter,
+                         "localize": tm.ms_localize, "total": tm.ms_total}
+    return out
 
 
 # ---------------------------------------------------------------- plane pairing

@@ -527,21 +527,19 @@ extern "C" int32_t ncc_localize(ulm_ctx_t *ctx, const float *filtered, ulm_loc_t
     return ULM_OK;
 }
 
-extern "C" int32_t ulm_reconstruct_ensemble(ulm_ctx_t *ctx, const float *iq, float *proj,
-                                            double *eigvals, ulm_loc_t *locs, int32_t capacity,
-                                            int32_t *count, void *ws, size_t ws_bytes,
-                                            ulm_timing_t *timing, void *stream) {
-    int32_t rc = check_ws(ctx, ws, ws_bytes);
-    if (rc) return rc;
-    if (!iq || !proj || !count || capacity < 0 || (capacity > 0 && !locs))
-        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+// beamform -> filter -> `localize` (a call of the same stream), with the
+// optional per-stage timing
+template <typename Loc>
+static int32_t reconstruct(ulm_ctx_t *ctx, const float *iq, float *proj, double *eigvals, void *ws,
+                           size_t ws_bytes, ulm_timing_t *timing, void *stream, Loc localize) {
     hipStream_t st = (hipStream_t)stream;
+    int32_t rc;
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[0], st), "hipEventRecord");
     if ((rc = rca_beamform_proj(ctx, iq, proj, ws, ws_bytes, stream))) return rc;
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[1], st), "hipEventRecord");
     if ((rc = svd_clutter_filter(ctx, proj, eigvals, ws, ws_bytes, stream))) return rc;
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[2], st), "hipEventRecord");
-    if ((rc = ncc_localize(ctx, proj, locs, capacity, count, ws, ws_bytes, stream))) return rc;
+    if ((rc = localize())) return rc;
     if (timing) {
         HIP_TRY(hipEventRecord(ctx->ev[3], st), "hipEventRecord");
         HIP_TRY(hipEventSynchronize(ctx->ev[3]), "hipEventSynchronize");
@@ -551,6 +549,19 @@ extern "C" int32_t ulm_reconstruct_ensemble(ulm_ctx_t *ctx, const float *iq, flo
         HIP_TRY(hipEventElapsedTime(&timing->ms_total, ctx->ev[0], ctx->ev[3]), "hipEventElapsedTime");
     }
     return ULM_OK;
+}
+
+extern "C" int32_t ulm_reconstruct_ensemble(ulm_ctx_t *ctx, const float *iq, float *proj,
+                                            double *eigvals, ulm_loc_t *locs, int32_t capacity,
+                                            int32_t *count, void *ws, size_t ws_bytes,
+                                            ulm_timing_t *timing, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!iq || !proj || !count || capacity < 0 || (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    return reconstruct(ctx, iq, proj, eigvals, ws, ws_bytes, timing, stream, [&] {
+        return ncc_localize(ctx, proj, locs, capacity, count, ws, ws_bytes, stream);
+    });
 }
 
 extern "C" int32_t ulm_check_status(ulm_ctx_t *ctx, void *ws, const int32_t *count,
@@ -719,6 +730,29 @@ extern "C" int32_t ulm_cnn_localize(ulm_ctx_t *ctx, const float *params, const f
                          g.nu, batch, fp32, locs, capacity, count, status, (char *)cnn_ws, st),
             "ulm_cnn_localize");
     return ULM_OK;
+}
+
+extern "C" int32_t ulm_reconstruct_ensemble_cnn(ulm_ctx_t *ctx, const float *iq, float *proj,
+                                                double *eigvals, const float *params, float threshold,
+                                                int32_t batch, int32_t precision, ulm_loc_t *locs,
+                                                int32_t capacity, int32_t *count, void *ws,
+                                                size_t ws_bytes, void *cnn_ws, size_t cnn_ws_bytes,
+                                                ulm_timing_t *timing, void *stream) {
+    int32_t rc = check_ws(ctx, ws, ws_bytes);
+    if (rc) return rc;
+    if (!iq || !proj || !params || !count || capacity < 0 || (capacity > 0 && !locs))
+        return fail(ULM_ERR_INVALID_ARG, "NULL argument or negative capacity");
+    // the CNN's own checks, before any work is queued
+    if ((rc = cnn_dims(batch, ctx->geo.nz, ctx->geo.nu, precision))) return rc;
+    if (!(threshold > -1e30f && threshold < 1e30f)) return fail(ULM_ERR_INVALID_ARG, "threshold not finite");
+    const int n_img = ctx->geo.n_planes * ctx->geo.n_frames;
+    if ((rc = check_cws(cnn_ws, cnn_ws_bytes,
+                        cnn_loc_workspace_bytes(batch, ctx->geo.nz, ctx->geo.nu, n_img, precision == ULM_CNN_FP32))))
+        return rc;
+    return reconstruct(ctx, iq, proj, eigvals, ws, ws_bytes, timing, stream, [&] {
+        return ulm_cnn_localize(ctx, params, proj, threshold, batch, precision, locs, capacity, count, ws,
+                                ws_bytes, cnn_ws, cnn_ws_bytes, stream);
+    });
 }
 
 // ---------------------------------------------------------------- plane pairing

@@ -248,6 +248,38 @@ def test_cnn_localize_fused_strips(torch, ulm, tiny_cfg, nz, nu):
         assert abs(float(r["intensity"]) - pz) <= 1e-6 * max(pz, 1e-30)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_cnn_whole_path_entry(torch, ulm, prec, tiny_cfg, tiny_iq):
+    """ulm_reconstruct_ensemble_cnn equals beamforming, filtering and
+    ulm_cnn_localize called one by one: the same filtered planes and the same
+    records, bit for bit; its timing covers the three stages."""
+    cfg = tiny_cfg
+    ctx = ulm.Context(cfg)
+    d = _dev(torch, tiny_iq, torch.complex64)
+    params = _dev(torch, ulm.cnn_pack(_params(4)), torch.float32)
+    pr = _prec(ulm, prec)
+    proj = ulm.rca_beamform_proj(ctx, d)
+    ulm.svd_clutter_filter(ctx, proj)
+    heat = ulm.ulm_cnn_forward(params, ulm.ulm_cnn_images(ctx, proj), pr).cpu().numpy()
+    thr, _ = _row_threshold(heat, cfg.seq.n_frames, cfg.grid.nu)
+    out = ulm.ulm_reconstruct_ensemble_cnn(ctx, d, params, 1 << 16, threshold=thr, batch=7,
+                                           precision=pr, timing=True)
+    ulm.ulm_check_status(ctx, out["count"], 1 << 16)
+    got = ulm.locs_to_numpy(out["locs"], out["count"]).copy()
+    locs, count = ulm.ulm_cnn_localize(ctx, params, proj, 1 << 16, threshold=thr, batch=7, precision=pr)
+    ulm.ulm_check_status(ctx, count, 1 << 16)
+    ref = ulm.locs_to_numpy(locs, count)
+    say(f"[cnn whole path {prec}] {len(got)} records, timing {out['timing']}")
+    assert len(got) > 0
+    assert torch.equal(out["proj"].view(torch.float32), proj.view(torch.float32))
+    assert got.tobytes() == ref.tobytes()
+    t = out["timing"]
+    assert t["total"] >= t["beamform"] + t["filter"] + t["localize"] - 1e-3
+    with pytest.raises(ulm.ULMError) as ei:
+        ulm.ulm_reconstruct_ensemble_cnn(ctx, d, params, 1 << 16, threshold=float("inf"), precision=pr)
+    assert ei.value.code == ulm.ULM_ERR_INVALID_ARG
+
+
 def test_cnn_row_overflow_flag(torch, ulm, tiny_cfg, tiny_iq):
     """A threshold below every heat value floods the per-row staging: the call
     keeps the first peaks of each row and ulm_check_status reports OVERFLOW

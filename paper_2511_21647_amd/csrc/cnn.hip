@@ -1447,20 +1447,22 @@ static hipError_t localize_t(const float *params, const float2 *P, const float *
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_compact(cnt, off, n_img * H, count, staged, L.row_cap, locs, capacity, st);
+    } else {
+        // FP32: layer by layer, `batch` images per pass, head and decode fused
+        for (int n0 = 0; n0 < n_img; n0 += batch) {
+            const int nb = std::min(batch, n_img - n0);
+            hipError_t e = cnn_images(P, fmax, x0, H * W, n0, nb, st);
+            if (e != hipSuccess) return e;
+            int last = 0;
+            if ((e = run_forward<T>(params, x0, act, 2, (T *)(cws + L.wm), (T *)(cws + L.wt), nb, H, W,
+                                    st, &last)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(cnn_head_decode_kernel<T>, dim3(cdiv(H, kHdRows), nb), dim3(256), 0, st,
+                               act[last], params, P, thr, H, W, n0, F, staged, cnt, L.row_cap, status);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        return launch_compact(cnt, off, n_img * H, count, staged, L.row_cap, locs, capacity, st);
     }
-    for (int n0 = 0; n0 < n_img; n0 += batch) {
-        const int nb = std::min(batch, n_img - n0);
-        hipError_t e = cnn_images(P, fmax, x0, H * W, n0, nb, st);
-        if (e != hipSuccess) return e;
-        int last = 0;
-        if ((e = run_forward<T>(params, x0, act, 2, (T *)(cws + L.wm), (T *)(cws + L.wt), nb, H, W,
-                                st, &last)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(cnn_head_decode_kernel<T>, dim3(cdiv(H, kHdRows), nb), dim3(256), 0, st, act[last],
-                           params, P, thr, H, W, n0, F, staged, cnt, L.row_cap, status);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return launch_compact(cnt, off, n_img * H, count, staged, L.row_cap, locs, capacity, st);
 }
 
 hipError_t cnn_localize(const float *params, const float2 *P, const float *fmax, float thr,

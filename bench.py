@@ -51,6 +51,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12      # 128 B per clock per CU
 # per channel-pixel-angle-frame evaluation: the complex interpolation as two
 # FMAs on the staged (sample, forward difference) pair, and the complex
 # multiply-accumulate by the phasor as four FMAs: 6 FMAs = 12 flop
@@ -482,10 +483,20 @@ def roofline(cfg, das_ms):
         rec = json.load(open(COUNTERS_FILE))
         if rec.get("source_sha") == source_hash():
             traffic = rec["hbm_bytes_per_launch"]
+    # the kernel's LDS traffic: 16 B of (sample, difference) read per evaluation,
+    # and per work-group (8 x 32 pixel tile, 16 frames, one transmit) and
+    # receive element 16 frames x 64 staged entries of 16 B written (the paper
+    # geometry's 64-sample window)
+    g = cfg.grid
+    wgs = -(-g.nu // 32) * -(-g.nz // 8) * -(-cfg.seq.n_frames // 16) * 2 * cfg.n_angles
+    lds_bytes = 16 * das_evals(cfg) + wgs * cfg.probe.n_elem * 16 * 64 * 16
+    lds_tbs = lds_bytes / (das_ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": "das_stage1_kernel", "achieved": round(achieved, 2),
             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
-            "algorithmic_flops": flops, "launch_ms": round(das_ms, 3)}
+            "algorithmic_flops": flops, "launch_ms": round(das_ms, 3),
+            "lds": {"bytes": lds_bytes, "achieved": round(lds_tbs, 2), "peak": LDS_PEAK_TBS,
+                    "unit": "TB/s", "frac": round(lds_tbs / LDS_PEAK_TBS, 4)}}
 
 
 def cpu_baseline(cfg):

@@ -44,9 +44,12 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
                                                        double2 *__restrict__ part, int F,
                                                        int npix, int pairs, int chunks, int nblk)
 {
-    const int chunk = blockIdx.x % chunks;
-    const int pair = (blockIdx.x / chunks) % pairs;
-    const int plane = blockIdx.x / (chunks * pairs);
+    // the block pairs of one pixel chunk run back to back on one XCD, so the
+    // frame blocks they share are read from that XCD's L2
+    const int wl = xcd_remap(blockIdx.x, gridDim.x);
+    const int pair = wl % pairs;
+    const int chunk = (wl / pairs) % chunks;
+    const int plane = wl / (chunks * pairs);
     int I, J;
     pair_of(pair, nblk, I, J);
     const float2 *src = P + (size_t)plane * F * npix;
@@ -222,9 +225,11 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(const float2 *__res
                                                              int nblk)
 {
     constexpr int NT = kSplitTerms;
-    const int chunk = blockIdx.x % chunks;
-    const int pair = (blockIdx.x / chunks) % pairs;
-    const int plane = blockIdx.x / (chunks * pairs);
+    // block pairs of one pixel chunk back to back on one XCD (shared frame blocks in its L2)
+    const int wl = xcd_remap(blockIdx.x, gridDim.x);
+    const int pair = wl % pairs;
+    const int chunk = (wl / pairs) % chunks;
+    const int plane = wl / (chunks * pairs);
     int I, J;
     pair_of(pair, nblk, I, J);
     const float2 *src = P + (size_t)plane * F * npix;

@@ -251,7 +251,7 @@ def _score_ensemble(e, n_mb, ncc, truth, cnn_by_thr):
 
 def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log, workers=4):
     """NCC and CNN on held-out ensembles: each against the truth, and the CNN
-    against NCC as the judge (all NCC detections, and NCC's true detections),
+    against NCC as the reference (all NCC detections, and NCC's true detections),
     for every CNN decode threshold given.  The matching runs in `workers` CPU
     processes, forked before the GPU is touched, while the GPU localises the
     next ensembles."""

@@ -398,13 +398,20 @@ __device__ inline void stage_head(const float *__restrict__ p, T *whs, float *bh
 }
 
 // One wave: 32 pixels (lane i32 supplies pixel `px`, or none when px < 0) x 64
-// head outputs.  acc[nb][q] = sum_c wh[32 nb + i32][c] a[pixel 8(q/4) + 4hk + q%4][c]
+// head outputs.  acc[nb][q] = bh[32 nb + i32] + sum_c wh[32 nb + i32][c] a[pixel
+// 8(q/4) + 4hk + q%4][c]: the MFMAs start from the bias, so every form of the
+// head (layer by layer and fused) rounds the same sums.
 template <typename T>
-__device__ inline void head_group(const T *__restrict__ act, long px, const T *whs, f32x16 acc[2]) {
+__device__ inline void head_group(const T *__restrict__ act, long px, const T *whs, const float *bhs,
+                                  f32x16 acc[2]) {
     constexpr int WS = Lds<T>::wh;
     const int lane = threadIdx.x & 63, i32 = lane & 31, hk = lane >> 5;
-    acc[0] = f32x16{};
-    acc[1] = f32x16{};
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const float b = bhs[nb * 32 + i32];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[nb][q] = b;
+    }
     if constexpr (sizeof(T) == 2) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -428,7 +435,7 @@ __device__ inline void head_group(const T *__restrict__ act, long px, const T *w
     }
 }
 
-// logits[px][k] = bh[k] + sum_c wh[k][c] a6[px][c]; 32 pixels per wave
+// logits[px][k] = bh[k] + sum_c wh[k][c] a6[px][c] (summed from the bias); 32 pixels per wave
 template <typename T>
 __global__ __launch_bounds__(256) void cnn_head_kernel(const T *__restrict__ a6,
                                                        const float *__restrict__ p,
@@ -443,14 +450,14 @@ __global__ __launch_bounds__(256) void cnn_head_kernel(const T *__restrict__ a6,
     if (base >= npx) return;
     const long mine = base + i32 < npx ? (long)(base + i32) : -1;
     f32x16 acc[2];
-    head_group<T>(a6, mine, whs, acc);
+    head_group<T>(a6, mine, whs, bhs, acc);
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const size_t px = base + 8 * (q >> 2) + 4 * hk + (q & 3);
             const int k = nb * 32 + i32;
-            if (px < npx) logits[px * kR2 + k] = acc[nb][q] + bhs[k];
+            if (px < npx) logits[px * kR2 + k] = acc[nb][q];
         }
 }
 
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(256, 2) void cnn_head_decode_kernel(
             const int yy = y0 + r - 1, xx = x0 + c - 1;
             const bool ok = s < NS && yy >= 0 && yy < H && xx >= 0 && xx < W;
             f32x16 acc[2];
-            head_group<T>(act, ok ? (long)yy * W + xx : -1L, whs, acc);
+            head_group<T>(act, ok ? (long)yy * W + xx : -1L, whs, bhs, acc);
             // row q of the 32 x 64 product belongs to slot gi * 32 + 8(q/4) + 4hk + q%4
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(256, 2) void cnn_head_decode_kernel(
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
                     const int k = nb * 32 + i32;
-                    hs[r2][c2][k] = okq ? acc[nb][q] + bhs[k] : -INFINITY;
+                    hs[r2][c2][k] = okq ? acc[nb][q] : -INFINITY;
                 }
             }
         }
@@ -633,9 +640,9 @@ __global__ __launch_bounds__(256, 2) void cnn_head_decode_kernel(
 constexpr int kFuseStrip = 50;                  // decode rows per strip at most
 constexpr int kFuseSlot = 66;                   // pixels per activation slot
 constexpr int kFuseHeatRows = kFuseStrip + 2;
-constexpr int kFuseHeatStride = kR2 + 1;        // decode lanes (8 rows x 8 fine rows) hit 64 banks
+constexpr int kFuseHeatStride = kR2 + 4;        // 16-byte aligned rows: the head writes float4
 constexpr int kFuseInRows = kFuseStrip + 14;
-constexpr int kFuseLagHead = 13, kFuseLagDecode = 15;
+constexpr int kFuseLagDecode = 14;
 constexpr int kFuseThreads = 768;
 
 __device__ inline int fuse_swz(int px) { return (px >> 1) & 3; }
@@ -646,7 +653,6 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
     ulm_loc_t *__restrict__ staged, int *__restrict__ row_cnt, int row_cap, int *__restrict__ status)
 {
     __shared__ __attribute__((aligned(16))) bf16 ring[5][4][kFuseSlot * kC];    // conv0 .. conv4 outputs
-    __shared__ __attribute__((aligned(16))) bf16 ring6[2][kFuseSlot * kC];      // conv5 output
     __shared__ float heat[4][kFuseHeatRows * kFuseHeatStride];
     __shared__ float x0r[4][kFuseInRows];
     __shared__ float inten[16][kFuseStrip];
@@ -660,6 +666,13 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
     for (int e = t; e < kW0 + kB0; e += kFuseThreads) w0s[e] = p[e];
     for (int e = t; e < (kL - 1) * kC; e += kFuseThreads) bcs[e / kC][e % kC] = p[off_b(1 + e / kC) + e % kC];
     stage_head<bf16>(p, whs, bhs);
+    // heat rows of the strip outside the image hold -inf in every slot; the head
+    // never writes them
+    for (int e = t; e < 4 * kFuseHeatRows * kR2; e += kFuseThreads) {
+        const int slot = e / (kFuseHeatRows * kR2), c = (e / kR2) % kFuseHeatRows, k = e % kR2;
+        const int row = ys - 1 + c;
+        if (row < 0 || row >= H) heat[slot][c * kFuseHeatStride + k] = -INFINITY;
+    }
     const int n_it = W + kFuseLagDecode;
 
     // Two role loops, one barrier per step in each, so the conv weights held
@@ -678,8 +691,8 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                     wr[tap][h] = *reinterpret_cast<const bf16x8 *>(wl + tap * kC + 16 * h + 8 * hk);
         }
         const bf16 *src = &ring[layer - 1][0][0];
-        bf16 *dst0 = layer < 5 ? &ring[layer][0][0] : &ring6[0][0];
-        const int dst_mask = layer < 5 ? 3 : 1, e_out = 6 - layer;
+        bf16 *dst0 = &ring[layer < 5 ? layer : 0][0][0];      // conv5 (layer 5) feeds the head directly
+        const int e_out = 6 - layer;
         const float *bl = bcs[layer - 1];
         // per-lane element offsets within a slot: the B operand of row offset dyy
         // and channel half h, and this lane's four output runs
@@ -730,7 +743,7 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                 // lane holds output channels 8 (q / 4) + 4 hk + q % 4 of index c
                 const int row = ys - e_out + c;
                 const bool ok = x >= 0 && x < W && c < SH + 2 * e_out && row >= 0 && row < H;
-                bf16 *dst = dst0 + (x & dst_mask) * kFuseSlot * kC;
+                uint2 pk[4];                  // this lane's 16 channels, BF16, in 4 runs of 4
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float4 b4 = *reinterpret_cast<const float4 *>(&bl[8 * r + 4 * hk]);
@@ -739,7 +752,71 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         v4[j] = fromf<bf16>(ok ? fmaxf(a[4 * r + j] + bb[j], 0.f) : 0.f);
-                    *reinterpret_cast<uint2 *>(dst + eoff[r]) = *reinterpret_cast<const uint2 *>(v4);
+                    pk[r] = *reinterpret_cast<const uint2 *>(v4);
+                }
+                if (layer < 5) {
+                    bf16 *dst = dst0 + (x & 3) * kFuseSlot * kC;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) *reinterpret_cast<uint2 *>(dst + eoff[r]) = pk[r];
+                } else {
+                    // ---- head (1x1, 32 -> 64) on this conv5 column, straight from the
+                    // registers: the B operand of K-half h is channels 16 h + 8 hk ..
+                    // + 7 of pixel c, half of them this lane's runs and half the runs of
+                    // lane i32 + 32 (hk 1) or i32 - 32 (hk 0), swapped across the halves.
+                    // Every lane takes part in the swaps and MFMAs (each lane supplies
+                    // an output row's weights); only rows c < SH + 2 are stored.
+                    float *hrow = &heat[x & 3][min(c, SH + 1) * kFuseHeatStride];
+                    const bool store = c < SH + 2;
+                    if (x >= 0 && x < W) {
+                        const uint2 s0 = hk ? pk[0] : pk[1], s1 = hk ? pk[2] : pk[3];
+                        uint2 r0, r1;
+                        {
+                            const auto u0 = __builtin_amdgcn_permlane32_swap(s0.x, s0.x, false, false);
+                            const auto u1 = __builtin_amdgcn_permlane32_swap(s0.y, s0.y, false, false);
+                            const auto u2 = __builtin_amdgcn_permlane32_swap(s1.x, s1.x, false, false);
+                            const auto u3 = __builtin_amdgcn_permlane32_swap(s1.y, s1.y, false, false);
+                            r0 = hk ? make_uint2(u0[0], u1[0]) : make_uint2(u0[1], u1[1]);
+                            r1 = hk ? make_uint2(u2[0], u3[0]) : make_uint2(u2[1], u3[1]);
+                        }
+                        const uint4 q0 = hk ? make_uint4(r0.x, r0.y, pk[1].x, pk[1].y)
+                                            : make_uint4(pk[0].x, pk[0].y, r0.x, r0.y);
+                        const uint4 q1 = hk ? make_uint4(r1.x, r1.y, pk[3].x, pk[3].y)
+                                            : make_uint4(pk[2].x, pk[2].y, r1.x, r1.y);
+                        const bf16x8 bh[2] = {__builtin_bit_cast(bf16x8, q0), __builtin_bit_cast(bf16x8, q1)};
+                        f32x16 hacc[2];
+#pragma unroll
+                        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const float4 b4 = *reinterpret_cast<const float4 *>(&bhs[nb * 32 + 8 * r + 4 * hk]);
+                                hacc[nb][4 * r + 0] = b4.x;
+                                hacc[nb][4 * r + 1] = b4.y;
+                                hacc[nb][4 * r + 2] = b4.z;
+                                hacc[nb][4 * r + 3] = b4.w;
+                            }
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int nb = 0; nb < 2; ++nb) {
+                                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+                                    whs + (nb * 32 + i32) * Lds<bf16>::wh + h * 16 + hk * 8);
+                                hacc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bh[h], hacc[nb], 0, 0, 0);
+                            }
+                        // rows outside the image keep the -inf written at the start
+                        if (store && row >= 0 && row < H) {
+#pragma unroll
+                            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    *reinterpret_cast<float4 *>(&hrow[nb * 32 + 8 * r + 4 * hk]) =
+                                        make_float4(hacc[nb][4 * r], hacc[nb][4 * r + 1], hacc[nb][4 * r + 2],
+                                                    hacc[nb][4 * r + 3]);
+                        }
+                    } else if (store) {
+                        const float4 ninf = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+#pragma unroll
+                        for (int k = 0; k < kR2; k += 4) *reinterpret_cast<float4 *>(&hrow[k]) = ninf;   // columns -1 and W
+                    }
                 }
             }
             // ---- decode: 3x3 local maxima of the fine heatmap at or above thr,
@@ -844,7 +921,7 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
             if (base > row_cap) atomicOr(status, kStatusCnnRow);
         }
     } else {
-        // ---- waves 10..11: the input (wave 11), conv0 and the head
+        // ---- waves 10..11: the input (wave 11) and conv0
         const int tau = t - 640;                     // 0 .. 127
         const float m = fmaxv[img];
         const int in_row = ys - 7 + lane;
@@ -853,7 +930,6 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
         auto in_load = [&](int x) { return in_ok && x < W ? prow[x] : make_float2(0.f, 0.f); };
         // the next two columns in flight
         float2 pf0 = in_load(0), pf1 = in_load(1);
-        const int c = 32 * (wave - 10) + i32;       // head: heat index of this lane
         __syncthreads();
         // conv0 items of this thread all have channel group tau & 3: its 8
         // channels' weights and biases stay in registers
@@ -906,44 +982,6 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                     }
                     *reinterpret_cast<uint4 *>(&ring[0][x & 3][(pi * 4 + (cc ^ fuse_swz(pi))) * 8]) =
                         *reinterpret_cast<const uint4 *>(res);
-                }
-            }
-            // ---- head (1x1, 32 -> 64) on conv5's column: 32 rows x 64 outputs per
-            // wave; columns -1 and W hold -inf
-            const int xh = it - kFuseLagHead;
-            if ((xh == -1 || xh == W) && c < SH + 2) {
-                float *hrow = &heat[xh & 3][c * kFuseHeatStride];
-#pragma unroll
-                for (int k = 0; k < kR2; ++k) hrow[k] = -INFINITY;
-            }
-            if (xh >= 0 && xh < W) {
-                f32x16 acc[2] = {{}, {}};
-                const bf16 *pix = &ring6[xh & 1][c * kC];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(pix + ((2 * h + hk) ^ fuse_swz(c)) * 8);
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb) {
-                        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
-                            whs + (nb * 32 + i32) * Lds<bf16>::wh + h * 16 + hk * 8);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[nb], 0, 0, 0);
-                    }
-                }
-                const int row = ys - 1 + c;
-                const bool ok = row >= 0 && row < H;
-                if (c < SH + 2) {
-                    float *hrow = &heat[xh & 3][c * kFuseHeatStride];
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int k = nb * 32 + 8 * r + 4 * hk;
-                            const float4 b4 = *reinterpret_cast<const float4 *>(&bhs[k]);
-                            hrow[k + 0] = ok ? acc[nb][4 * r + 0] + b4.x : -INFINITY;
-                            hrow[k + 1] = ok ? acc[nb][4 * r + 1] + b4.y : -INFINITY;
-                            hrow[k + 2] = ok ? acc[nb][4 * r + 2] + b4.z : -INFINITY;
-                            hrow[k + 3] = ok ? acc[nb][4 * r + 3] + b4.w : -INFINITY;
-                        }
                 }
             }
             __syncthreads();

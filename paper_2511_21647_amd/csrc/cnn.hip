@@ -642,7 +642,7 @@ constexpr int kFuseSlot = 66;                   // pixels per activation slot
 constexpr int kFuseHeatRows = kFuseStrip + 2;
 constexpr int kFuseHeatStride = kR2 + 4;        // 16-byte aligned rows: the head writes float4
 constexpr int kFuseInRows = kFuseStrip + 14;
-constexpr int kFuseLagDecode = 14;
+constexpr int kFuseLagHead = 13, kFuseLagDecode = 15;
 constexpr int kFuseThreads = 768;
 
 __device__ inline int fuse_swz(int px) { return (px >> 1) & 3; }
@@ -653,6 +653,7 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
     ulm_loc_t *__restrict__ staged, int *__restrict__ row_cnt, int row_cap, int *__restrict__ status)
 {
     __shared__ __attribute__((aligned(16))) bf16 ring[5][4][kFuseSlot * kC];    // conv0 .. conv4 outputs
+    __shared__ __attribute__((aligned(16))) bf16 ring6[2][kFuseSlot * kC];      // conv5 output
     __shared__ float heat[4][kFuseHeatRows * kFuseHeatStride];
     __shared__ float x0r[4][kFuseInRows];
     __shared__ float inten[16][kFuseStrip];
@@ -691,8 +692,8 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                     wr[tap][h] = *reinterpret_cast<const bf16x8 *>(wl + tap * kC + 16 * h + 8 * hk);
         }
         const bf16 *src = &ring[layer - 1][0][0];
-        bf16 *dst0 = &ring[layer < 5 ? layer : 0][0][0];      // conv5 (layer 5) feeds the head directly
-        const int e_out = 6 - layer;
+        bf16 *dst0 = layer < 5 ? &ring[layer][0][0] : &ring6[0][0];
+        const int dst_mask = layer < 5 ? 3 : 1, e_out = 6 - layer;
         const float *bl = bcs[layer - 1];
         // per-lane element offsets within a slot: the B operand of row offset dyy
         // and channel half h, and this lane's four output runs
@@ -711,8 +712,30 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
         const int dy_rel = t >> 3, dfi = t & 7, dy = ys + dy_rel;
         const bool dec_ok = wave < 7 && dy_rel < SH && dy < H;
         int base = 0;
+        // input lanes (wave 7): row ys - 7 + lane, the next two columns in flight
+        const float m = fmaxv[img];
+        const int in_row = ys - 7 + lane;
+        const bool in_ok = wave == 7 && lane < SH + 14 && in_row >= 0 && in_row < H;
+        const float2 *prow = P + ((size_t)img * H + (in_ok ? in_row : 0)) * W;
+        auto in_load = [&](int x) { return in_ok && x < W ? prow[x] : make_float2(0.f, 0.f); };
+        float2 pf0 = in_load(0), pf1 = in_load(1);
         __syncthreads();
         for (int it = -1; it < n_it; ++it) {
+            // ---- input: x0 = |P| / frame max (0 outside the image), |P| kept for the
+            // records; columns -1 and W are zero
+            if (wave == 7 && it <= W) {
+                float2 v = make_float2(0.f, 0.f);
+                if (it >= 0 && it < W) {
+                    v = pf0;
+                    pf0 = pf1;
+                    pf1 = in_load(it + 2);
+                }
+                if (lane < SH + 14) {
+                    const float mag = cnn_mag(v);
+                    x0r[it & 3][lane] = m > 0.f ? mag / m : 0.f;
+                    if (lane >= 7 && lane < 7 + SH && it >= 0 && it < W) inten[it & 15][lane - 7] = mag;
+                }
+            }
             // columns -1 and W are written as zeros, so every read below is unconditional
             const int x = it - 2 * (layer + 1);
             if (x >= -1 && x <= W) {
@@ -754,70 +777,9 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                         v4[j] = fromf<bf16>(ok ? fmaxf(a[4 * r + j] + bb[j], 0.f) : 0.f);
                     pk[r] = *reinterpret_cast<const uint2 *>(v4);
                 }
-                if (layer < 5) {
-                    bf16 *dst = dst0 + (x & 3) * kFuseSlot * kC;
+                bf16 *dst = dst0 + (x & dst_mask) * kFuseSlot * kC;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) *reinterpret_cast<uint2 *>(dst + eoff[r]) = pk[r];
-                } else {
-                    // ---- head (1x1, 32 -> 64) on this conv5 column, straight from the
-                    // registers: the B operand of K-half h is channels 16 h + 8 hk ..
-                    // + 7 of pixel c, half of them this lane's runs and half the runs of
-                    // lane i32 + 32 (hk 1) or i32 - 32 (hk 0), swapped across the halves.
-                    // Every lane takes part in the swaps and MFMAs (each lane supplies
-                    // an output row's weights); only rows c < SH + 2 are stored.
-                    float *hrow = &heat[x & 3][min(c, SH + 1) * kFuseHeatStride];
-                    const bool store = c < SH + 2;
-                    if (x >= 0 && x < W) {
-                        const uint2 s0 = hk ? pk[0] : pk[1], s1 = hk ? pk[2] : pk[3];
-                        uint2 r0, r1;
-                        {
-                            const auto u0 = __builtin_amdgcn_permlane32_swap(s0.x, s0.x, false, false);
-                            const auto u1 = __builtin_amdgcn_permlane32_swap(s0.y, s0.y, false, false);
-                            const auto u2 = __builtin_amdgcn_permlane32_swap(s1.x, s1.x, false, false);
-                            const auto u3 = __builtin_amdgcn_permlane32_swap(s1.y, s1.y, false, false);
-                            r0 = hk ? make_uint2(u0[0], u1[0]) : make_uint2(u0[1], u1[1]);
-                            r1 = hk ? make_uint2(u2[0], u3[0]) : make_uint2(u2[1], u3[1]);
-                        }
-                        const uint4 q0 = hk ? make_uint4(r0.x, r0.y, pk[1].x, pk[1].y)
-                                            : make_uint4(pk[0].x, pk[0].y, r0.x, r0.y);
-                        const uint4 q1 = hk ? make_uint4(r1.x, r1.y, pk[3].x, pk[3].y)
-                                            : make_uint4(pk[2].x, pk[2].y, r1.x, r1.y);
-                        const bf16x8 bh[2] = {__builtin_bit_cast(bf16x8, q0), __builtin_bit_cast(bf16x8, q1)};
-                        f32x16 hacc[2];
-#pragma unroll
-                        for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const float4 b4 = *reinterpret_cast<const float4 *>(&bhs[nb * 32 + 8 * r + 4 * hk]);
-                                hacc[nb][4 * r + 0] = b4.x;
-                                hacc[nb][4 * r + 1] = b4.y;
-                                hacc[nb][4 * r + 2] = b4.z;
-                                hacc[nb][4 * r + 3] = b4.w;
-                            }
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-#pragma unroll
-                            for (int nb = 0; nb < 2; ++nb) {
-                                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
-                                    whs + (nb * 32 + i32) * Lds<bf16>::wh + h * 16 + hk * 8);
-                                hacc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bh[h], hacc[nb], 0, 0, 0);
-                            }
-                        // rows outside the image keep the -inf written at the start
-                        if (store && row >= 0 && row < H) {
-#pragma unroll
-                            for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                                for (int r = 0; r < 4; ++r)
-                                    *reinterpret_cast<float4 *>(&hrow[nb * 32 + 8 * r + 4 * hk]) =
-                                        make_float4(hacc[nb][4 * r], hacc[nb][4 * r + 1], hacc[nb][4 * r + 2],
-                                                    hacc[nb][4 * r + 3]);
-                        }
-                    } else if (store) {
-                        const float4 ninf = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
-#pragma unroll
-                        for (int k = 0; k < kR2; k += 4) *reinterpret_cast<float4 *>(&hrow[k]) = ninf;   // columns -1 and W
-                    }
-                }
+                for (int r = 0; r < 4; ++r) *reinterpret_cast<uint2 *>(dst + eoff[r]) = pk[r];
             }
             // ---- decode: 3x3 local maxima of the fine heatmap at or above thr,
             // records in (coarse column, fine row, fine column) order within each row
@@ -921,15 +883,11 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
             if (base > row_cap) atomicOr(status, kStatusCnnRow);
         }
     } else {
-        // ---- waves 10..11: the input (wave 11) and conv0
+        // ---- waves 10..11: conv0 and the head
         const int tau = t - 640;                     // 0 .. 127
-        const float m = fmaxv[img];
-        const int in_row = ys - 7 + lane;
-        const bool in_ok = wave == 11 && lane < SH + 14 && in_row >= 0 && in_row < H;
-        const float2 *prow = P + ((size_t)img * H + (in_ok ? in_row : 0)) * W;
-        auto in_load = [&](int x) { return in_ok && x < W ? prow[x] : make_float2(0.f, 0.f); };
-        // the next two columns in flight
-        float2 pf0 = in_load(0), pf1 = in_load(1);
+        const int c = 32 * (wave - 10) + i32;       // head: heat index of this lane
+        float *const hrow0 = &heat[0][min(c, SH + 1) * kFuseHeatStride];
+        const bool store = c < SH + 2, okh = store && ys - 1 + c >= 0 && ys - 1 + c < H;
         __syncthreads();
         // conv0 items of this thread all have channel group tau & 3: its 8
         // channels' weights and biases stay in registers
@@ -942,21 +900,6 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
             b0r[o8] = w0s[kW0 + 8 * cc + o8];
         }
         for (int it = -1; it < n_it; ++it) {
-            // ---- input: x0 = |P| / frame max (0 outside the image), |P| kept for the
-            // records; columns -1 and W are zero
-            if (wave == 11 && it >= -1 && it <= W) {
-                float2 v = make_float2(0.f, 0.f);
-                if (it >= 0 && it < W) {
-                    v = pf0;
-                    pf0 = pf1;
-                    pf1 = in_load(it + 2);
-                }
-                if (lane < SH + 14) {
-                    const float mag = cnn_mag(v);
-                    x0r[it & 3][lane] = m > 0.f ? mag / m : 0.f;
-                    if (lane >= 7 && lane < 7 + SH && it >= 0 && it < W) inten[it & 15][lane - 7] = mag;
-                }
-            }
             // ---- conv0 (1 -> 32): item = (output index, 8-channel group)
             const int x = it - 2;
             if (x >= -1 && x <= W) {
@@ -982,6 +925,49 @@ __global__ __launch_bounds__(kFuseThreads, 1) void cnn_localize_fused_kernel(
                     }
                     *reinterpret_cast<uint4 *>(&ring[0][x & 3][(pi * 4 + (cc ^ fuse_swz(pi))) * 8]) =
                         *reinterpret_cast<const uint4 *>(res);
+                }
+            }
+            // ---- head (1x1, 32 -> 64) on conv5's column: 32 rows x 64 outputs per
+            // wave, the MFMAs started from the bias; rows outside the image keep
+            // the -inf written at the start, columns -1 and W are all -inf
+            const int xh = it - kFuseLagHead;
+            float *hrow = hrow0 + (xh & 3) * kFuseHeatRows * kFuseHeatStride;
+            if ((xh == -1 || xh == W) && store) {
+                const float4 ninf = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+#pragma unroll
+                for (int k = 0; k < kR2; k += 4) *reinterpret_cast<float4 *>(&hrow[k]) = ninf;
+            }
+            if (xh >= 0 && xh < W) {
+                f32x16 hacc[2];
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float4 b4 = *reinterpret_cast<const float4 *>(&bhs[nb * 32 + 8 * r + 4 * hk]);
+                        hacc[nb][4 * r + 0] = b4.x;
+                        hacc[nb][4 * r + 1] = b4.y;
+                        hacc[nb][4 * r + 2] = b4.z;
+                        hacc[nb][4 * r + 3] = b4.w;
+                    }
+                const bf16 *pix = &ring6[xh & 1][c * kC];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(pix + ((2 * h + hk) ^ fuse_swz(c)) * 8);
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb) {
+                        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+                            whs + (nb * 32 + i32) * Lds<bf16>::wh + h * 16 + hk * 8);
+                        hacc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, hacc[nb], 0, 0, 0);
+                    }
+                }
+                if (okh) {
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            *reinterpret_cast<float4 *>(&hrow[nb * 32 + 8 * r + 4 * hk]) =
+                                make_float4(hacc[nb][4 * r], hacc[nb][4 * r + 1], hacc[nb][4 * r + 2],
+                                            hacc[nb][4 * r + 3]);
                 }
             }
             __syncthreads();

@@ -94,6 +94,38 @@ def das_evals(cfg) -> int:
     return 2 * cfg.n_angles * cfg.seq.n_frames * g.nz * g.nu * cfg.probe.n_elem
 
 
+def das_staged_entries(cfg) -> int:
+    """Staged (sample, difference) entries of one frame summed over every
+    (transmit, 8 x 32 tile, receive element): each window is staged in 16-sample
+    chunks from the first to the last sample the tile reads (the library's host
+    rule, with its FP32 sum of receive and transmit delay)."""
+    import numpy as np
+    p, g, q = cfg.probe, cfg.grid, cfg.seq
+    z = g.z0 + np.arange(g.nz) * g.dz
+    u = g.u0 + np.arange(g.nu) * g.du
+    ue = (np.arange(p.n_elem) - 0.5 * (p.n_elem - 1)) * p.pitch
+    dx = u[None, None, :] - ue[:, None, None]
+    zz = z[None, :, None]
+    rxd = (dx * dx / (np.sqrt(dx * dx + zz * zz) + zz) * p.fs / p.c).astype(np.float32)
+    L = (p.n_elem - 1) * p.pitch
+    ntz, ntu = -(-g.nz // 8), -(-g.nu // 32)
+    total = 0
+    for th in np.deg2rad(np.asarray(q.angles_deg, dtype=np.float64)):
+        ttx = (z * np.cos(th) + g.v_ref * np.sin(th) + 0.5 * L * abs(np.sin(th))) / p.c
+        sfull = (ttx + z / p.c - q.t_start) * p.fs
+        sti = np.floor(sfull)
+        stx = (sfull - sti).astype(np.float32)
+        idx = np.floor(rxd + stx[None, :, None]).astype(np.int64) + sti.astype(np.int64)[None, :, None]
+        pad_hi = np.full((p.n_elem, ntz * 8, ntu * 32), np.iinfo(np.int64).min)
+        pad_lo = np.full((p.n_elem, ntz * 8, ntu * 32), np.iinfo(np.int64).max)
+        pad_hi[:, :g.nz, :g.nu] = idx
+        pad_lo[:, :g.nz, :g.nu] = idx
+        hi = pad_hi.reshape(p.n_elem, ntz, 8, ntu, 32).max(axis=(2, 4))
+        lo = pad_lo.reshape(p.n_elem, ntz, 8, ntu, 32).min(axis=(2, 4))
+        total += int((16 * -(-(hi - lo + 1) // 16)).sum())
+    return 2 * total
+
+
 WEIGHTS = os.path.join(ROOT, "paper_2511_21647_amd", "weights", "cnn_paper.npy")
 
 
@@ -485,11 +517,9 @@ def roofline(cfg, das_ms):
             traffic = rec["hbm_bytes_per_launch"]
     # the kernel's LDS traffic: 16 B of (sample, difference) read per evaluation,
     # and per work-group (8 x 32 pixel tile, 16 frames, one transmit) and
-    # receive element 16 frames x 64 staged entries of 16 B written (the paper
-    # geometry's 64-sample window)
-    g = cfg.grid
-    wgs = -(-g.nu // 32) * -(-g.nz // 8) * -(-cfg.seq.n_frames // 16) * 2 * cfg.n_angles
-    lds_bytes = 16 * das_evals(cfg) + wgs * cfg.probe.n_elem * 16 * 64 * 16
+    # receive element the window's staged entries of 16 B written for 16 frames
+    frame_blocks = -(-cfg.seq.n_frames // 16)
+    lds_bytes = 16 * das_evals(cfg) + das_staged_entries(cfg) * 16 * 16 * frame_blocks
     lds_tbs = lds_bytes / (das_ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": "das_stage1_kernel", "achieved": round(achieved, 2),
             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -218,7 +218,9 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
         }
     }
     // DAS windows: for every (transmit, tile, element) the first sample any pixel
-    // of the tile reads, from the same FP32 sum s = rxd + stx the kernel forms
+    // of the tile reads, from the same FP32 sum s = rxd + stx the kernel forms,
+    // and the number of 16-sample chunks from there to the last one it reads,
+    // packed as start * 16 + (chunks - 1)
     const int n_tu = cdiv(c.nu, kDasTileU), n_tz = cdiv(c.nz, kDasTileZ), n_tiles = n_tu * n_tz;
     std::vector<int> win((size_t)c.n_angles * n_tiles * c.n_elem);
     int wspan = 0;
@@ -238,7 +240,8 @@ extern "C" int32_t ulm_create(const ulm_config_t *cfg, ulm_ctx_t **out) {
                             hi = std::max(hi, fl);
                         }
                     }
-                    win[((size_t)k * n_tiles + (tz * n_tu + tu)) * c.n_elem + e] = lo;
+                    const int chunks = cdiv(hi - lo + 1, 16);
+                    win[((size_t)k * n_tiles + (tz * n_tu + tu)) * c.n_elem + e] = lo * 16 + (chunks - 1);
                     wspan = std::max(wspan, hi - lo + 1);
                 }
     const int das_len = wspan <= 64 ? 64 : (wspan <= 128 ? 128 : 0);

@@ -68,7 +68,7 @@ struct Tables {
     float2 *phz;       // [K][Nz]   exp(i 2 pi f0 (tau_tx - z / c))
     float *rxd;        // [Nc][Nz*Nu] (r - z) * fs / c
     float2 *rxp;       // [Nc][Nz*Nu] exp(i 2 pi f0 (r - z) / c)
-    int *win;          // [K][tiles][Nc] first staged sample of each DAS window
+    int *win;          // [K][tiles][Nc] DAS window: first staged sample * 16 + (16-sample chunks - 1)
     int das_len;       // staged samples per window (64 or 128)
     float2 *taps;      // [K][B][T] stage-2 axial FIR taps (first meta.y used)
     int2 *tap_meta;    // [K][B]    (first tap offset, number of taps)

@@ -3,10 +3,10 @@
 // S_k(u, z).  One work-group owns an 8 x 32 pixel tile, one transmit and 16
 // frames: the delay, interpolation weight and phasor of each (pixel, element)
 // pair are read once and applied to all 16 frames.  For each element the
-// samples that the tile can reach (at most 64 or 128, exact window from the
-// host) are staged in LDS, double-buffered: the next element's global loads are
-// in flight during the current element's arithmetic, so the gathers hit LDS,
-// not the cache.
+// samples that the tile reads (the exact window from the host, staged in
+// 16-sample chunks, at most 64 or 128 samples) are staged in LDS,
+// double-buffered: the next element's global loads are in flight during the
+// current element's arithmetic, so the gathers hit LDS, not the cache.
 #include "common.h"
 
 namespace ulm {
@@ -22,17 +22,22 @@ namespace ulm {
 // element) window start win[...] exactly.
 // LDS holds, per staged sample, (IQ[s], IQ[s+1] - IQ[s]) so the interpolation
 // is two FMAs per frame.
-// Staging map and LDS slots.  Thread e stages run `run` (samples 4 run ..
-// 4 run + 3 and their differences) of frame `fl`:
-//   fl  = 4 (e / 4R) + (e / 4) % 4,   run = e % 4 + 4 ((e % 4R) / 16),   R = runs per frame,
-// so each lane quad loads 4 consecutive runs of one frame (one 128-byte span).
+// Staging: the window of a (transmit, tile, element) is staged in chunks of 16
+// samples x 16 frames, one chunk per wave and step; only the chunks the tile
+// reads are staged (the host packs the count beside the window start).  In a
+// chunk, lane l stages frame l / 4, run l % 4 (4 samples and their differences),
+// so each lane quad loads 17 consecutive samples of one frame.  Which wave
+// stages which chunk rotates with the element, so the staging work, and the
+// waves that skip it, spread evenly over the SIMDs.
 // LDS serves 128 bytes (8 lanes of a 16-byte access) per clock; entry n of
 // frame f sits in slot n ^ (2 (f % 2) + (n / 8) % 2), which gives the 8 stores
 // of two quads 8 different 16-byte bank groups and keeps consecutive entries
 // of a frame in different bank groups for the reads.
 __device__ inline int das_slot(int f, int n) { return n ^ ((2 * (f & 1) + ((n >> 3) & 1)) & 3); }
-template <int RUNS> __device__ inline int das_frame(int e) { return 4 * (e / (4 * RUNS)) + ((e >> 2) & 3); }
-template <int RUNS> __device__ inline int das_run(int e) { return (e & 3) + 4 * ((e % (4 * RUNS)) >> 4); }
+constexpr int kDasChunk = 16;
+// window word: start * 16 + (chunks - 1)
+__device__ inline int das_lo(int w) { return w >> 4; }
+__device__ inline int das_chunks(int w) { return (w & 15) + 1; }
 
 template <int FB, int LEN>
 __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
@@ -71,62 +76,68 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     const int f0 = fb * FB;
     const float2 *blk = iq + ((size_t)o * g.n_angles + k) * g.n_elem * g.n_samp;
 
-    // staging map: each thread stages runs of 4 consecutive samples of one frame
-    // (5 loads give the 4 samples and their 4 forward differences)
-    constexpr int RUNS = LEN / 4;
-    constexpr int NQ = FB * RUNS / kDasThreads;
-    static_assert(NQ >= 1 && FB * RUNS % kDasThreads == 0, "staging map");
+    // each wave stages NQ chunks per element: chunk (wave + j + 4 q) % NC
+    constexpr int NC = LEN / kDasChunk;
+    constexpr int NQ = NC / 4;
+    static_assert(kDasThreads == 256 && FB == 16 && NQ >= 1 && NC % 4 == 0, "staging map");
+    const int lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int sfl = lane >> 2;                 // staged frame
+    const int srun = lane & 3;                 // run of 4 samples within the chunk
+    // frames past the end read the last frame; their sums are never written
+    const float2 *srow = blk + (size_t)min(f0 + sfl, g.n_frames - 1) * frame_stride;
+    auto chunk_of = [&](int j, int q) { return (wave + j + 4 * q) & (NC - 1); };
     // two register sets: the global loads of element j + 2 are in flight while
     // element j is applied and element j + 1 (loaded one step earlier) is stored.
     // The loads write their registers unconditionally (start clamped into the
-    // record), so nothing waits on them before the store; a window that crosses
+    // record), so nothing waits on them before the store; a chunk that crosses
     // an end of the record is read again, sample by sample with zeros outside,
-    // at the store.
+    // at the store.  A wave whose chunk lies past the window skips both.
     float2 sa[NQ][5], sb[NQ][5];
-    auto row_of = [&](int j, int q) {
-        const int fl = das_frame<RUNS>(t + q * kDasThreads);
-        // frames past the end read the last frame; their sums are never written
-        return blk + (size_t)j * g.n_samp + (size_t)min(f0 + fl, g.n_frames - 1) * frame_stride;
-    };
     auto load = [&](int j, float2 (&st)[NQ][5]) {
-        const int s_lo = wj[j];
+        const int wj_ = wj[j];
+        const int s_lo = das_lo(wj_), nch = das_chunks(wj_);
+        const float2 *row = srow + (size_t)j * g.n_samp;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int run = das_run<RUNS>(t + q * kDasThreads);
-            const float2 *row = row_of(j, q);
-            const int gs = max(min(s_lo + 4 * run, g.n_samp - 5), 0);
+            const int c = chunk_of(j, q);
+            if (c < nch) {
+                const int gs = max(min(s_lo + kDasChunk * c + 4 * srun, g.n_samp - 5), 0);
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st[q][i] = row[gs + i];
+                for (int i = 0; i < 5; ++i) st[q][i] = row[gs + i];
+            }
         }
     };
     // the registers hold the five raw samples until the store, which forms the
-    // four (sample, difference) entries.  A window that crosses an end of the
-    // record (a uniform branch) is read again at the store, sample by sample
-    // with zeros outside the record, and those values are written instead.
-    auto store = [&](int b, int j, int s_lo, const float2 (&st)[NQ][5]) {
-        const bool inside = s_lo >= 0 && s_lo + LEN < g.n_samp;
+    // four (sample, difference) entries
+    auto store = [&](int b, int j, int wj_, const float2 (&st)[NQ][5]) {
+        const int s_lo = das_lo(wj_), nch = das_chunks(wj_);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int e = t + q * kDasThreads;
-            const int fl = das_frame<RUNS>(e), run = das_run<RUNS>(e);
-            float2 x[5];
-            if (inside) {
+            const int c = chunk_of(j, q);
+            if (c < nch) {
+                const int s0 = s_lo + kDasChunk * c;
+                const bool inside = s0 >= 0 && s0 + kDasChunk < g.n_samp;
+                float2 x[5];
+                if (inside) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) x[i] = st[q][i];
-            } else {
-                const float2 *row = row_of(j, q);
+                    for (int i = 0; i < 5; ++i) x[i] = st[q][i];
+                } else {
+                    const float2 *row = srow + (size_t)j * g.n_samp;
 #pragma unroll
-                for (int i = 0; i < 5; ++i) {
-                    const int gi = s_lo + 4 * run + i;
-                    const float2 v = row[min(max(gi, 0), g.n_samp - 1)];
-                    const bool ok = gi >= 0 && gi < g.n_samp;
-                    x[i] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);
+                    for (int i = 0; i < 5; ++i) {
+                        const int gi = s0 + 4 * srun + i;
+                        const float2 v = row[min(max(gi, 0), g.n_samp - 1)];
+                        const bool ok = gi >= 0 && gi < g.n_samp;
+                        x[i] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);
+                    }
                 }
-            }
+                const int n0 = kDasChunk * c + 4 * srun;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                buf[b][fl][das_slot(fl, 4 * run + i)] =
-                    make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
+                for (int i = 0; i < 4; ++i)
+                    buf[b][sfl][das_slot(sfl, n0 + i)] =
+                        make_float4(x[i].x, x[i].y, x[i + 1].x - x[i].x, x[i + 1].y - x[i].y);
+            }
         }
     };
 
@@ -165,34 +176,34 @@ __global__ __launch_bounds__(kDasThreads) void das_stage1_kernel(
     // the receive delay and phasor of the element being applied, and of the next
     float crx = rxd[pix], nrx;
     float2 cph = rxp[pix], nph;
-    int s_lo = wj[0];
+    int s_lo = das_lo(wj[0]);
     load(min(1, last), sb);
     __syncthreads();
     // the last steps re-stage the last element into the idle buffer, so the
     // loop body has no branch around the stores
     for (int j = 0; j < n; j += 2) {
         // buf[0] holds element j, sb element j + 1
-        int s_nx = wj[min(j + 1, last)];
+        int w_nx = wj[min(j + 1, last)];
         load(min(j + 2, last), sa);
         nrx = rxd[(size_t)min(j + 1, last) * npix + pix];
         nph = rxp[(size_t)min(j + 1, last) * npix + pix];
         apply(0, crx, cph, s_lo);
-        store(1, min(j + 1, last), s_nx, sb);
+        store(1, min(j + 1, last), w_nx, sb);
         crx = nrx;
         cph = nph;
-        s_lo = s_nx;
+        s_lo = das_lo(w_nx);
         __syncthreads();
         if (j + 1 < n) {
             // buf[1] holds element j + 1, sa element j + 2
-            s_nx = wj[min(j + 2, last)];
+            w_nx = wj[min(j + 2, last)];
             load(min(j + 3, last), sb);
             nrx = rxd[(size_t)min(j + 2, last) * npix + pix];
             nph = rxp[(size_t)min(j + 2, last) * npix + pix];
             apply(1, crx, cph, s_lo);
-            store(0, min(j + 2, last), s_nx, sa);
+            store(0, min(j + 2, last), w_nx, sa);
             crx = nrx;
             cph = nph;
-            s_lo = s_nx;
+            s_lo = das_lo(w_nx);
             __syncthreads();
         }
     }

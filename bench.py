@@ -734,6 +734,10 @@ def _kernel_work(name, wgs, gy, gz):
             return ("mfma", flops, "flop", FP64_PEAK_TFLOPS, f"{planes} planes, FP64 MFMA")
         return ("mfma", flops, "flop", BF16_PEAK_TFLOPS,
                 f"{planes} planes; the split form issues 6 BF16 products per real product")
+    if "removal_f64_kernel" in short:
+        planes = gy
+        return ("mfma", planes * 16.0 * F_P * C_P * NPIX_P, "flop", FP64_PEAK_TFLOPS,
+                f"{planes} planes, two products of F x c complex MACs per pixel, FP64 MFMA")
     if "removal" in short and "tables" not in short:
         planes = gy
         return ("hbm", 2 * planes * plane_bytes, "byte", HBM_PEAK_GBS / 1e3,

@@ -147,7 +147,12 @@ static void layout_workspace(ulm_ctx *ctx) {
     w.offd = take(sizeof(double) * planes * F);
     w.evals = take(sizeof(double) * planes * F);
     w.evecs = take(sizeof(double2) * planes * F * cc);
-    w.vpad = take(sizeof(double2) * planes * F * removal_cols(c.svd_cutoff));
+    if (c.precision != ULM_PREC_BF16X3 && c.svd_cutoff > 0) {
+        const Removal64Dims rd = removal64_dims(c.n_frames, c.svd_cutoff);
+        w.rtab64 = take(sizeof(double) * planes * (rd.t1_plane + rd.t2_plane));
+    } else {
+        w.rtab64 = take(0);
+    }
     if (c.precision == ULM_PREC_BF16X3 && c.svd_cutoff > 0) {
         const RemovalDims rd = removal_dims(c.n_frames, c.svd_cutoff);
         w.rtab = take(16 * planes * (rd.t1_plane + rd.t2_plane));

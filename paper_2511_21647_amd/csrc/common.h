@@ -30,6 +30,26 @@ constexpr int kNccMaxHalf = 7;     // template half-width limit (size <= 15)
 // and the shape of the removal's per-plane MFMA operand tables (built from the
 // clutter eigenvectors), counted in 16-byte lane operands (8 BF16 values).
 constexpr int kSplitTerms = 3;
+// FP64 removal on the matrix cores (16 x 16 x 4 tiles): operand tables per plane.
+struct Removal64Dims {
+    int MT;            // 16-row tiles of the 2c real rows of (I V_c)^T (c <= 32: at most 4)
+    int KS1;           // K-steps of I V_c: (re, im) per 4 frames
+    int FT;            // 8-frame tiles of the output
+    int KS2;           // K-steps (4 real rows each, all MT tiles) of (I V_c) V_c^H
+    size_t t1_plane;   // doubles per plane, first product
+    size_t t2_plane;   // doubles per plane, second product
+};
+inline Removal64Dims removal64_dims(int F, int c) {
+    Removal64Dims d;
+    d.MT = (2 * c + 15) / 16;
+    d.KS1 = 2 * ((F + 3) / 4);
+    d.FT = (F + 7) / 8;
+    d.KS2 = 4 * d.MT;
+    d.t1_plane = (size_t)d.MT * d.KS1 * 64;
+    d.t2_plane = (size_t)d.FT * d.KS2 * 64;
+    return d;
+}
+
 struct RemovalDims {
     int MT;            // 32-row tiles of the 2c real rows of (I V_c)^T
     int S1;            // K-steps (8 frames each) of I V_c
@@ -97,7 +117,7 @@ struct Workspace {
     size_t offd;        // [planes][F] f64
     size_t evals;       // [planes][F] f64          descending
     size_t evecs;       // [planes][F][c] c128
-    size_t vpad;        // [planes][F][removal_cols(c)] c128, zero past column c
+    size_t rtab64;      // [planes][t1_plane + t2_plane] f64 operands (FP64 removal)
     size_t rtab;        // [planes][t1_plane + t2_plane] BF16 x 8 operands (split removal only)
     size_t xprof;       // [2][K][B][F][Nz] c64 slab sums of the stage-1 slices (cross projection)
     size_t tscratch;    // [planes][c][6][F] f64    inverse-iteration scratch
@@ -118,7 +138,6 @@ struct Workspace {
 template <typename T> __host__ __device__ inline T cdiv(T a, T b) { return (a + b - 1) / b; }
 
 // Columns of the padded clutter subspace the removal kernel is compiled for.
-inline int removal_cols(int c) { return c <= 4 ? 4 : c <= 8 ? 8 : c <= 12 ? 12 : c <= 16 ? 16 : c <= 20 ? 20 : c <= 24 ? 24 : 32; }
 
 // Work-group remap so that consecutive logical work-groups land on the same
 // XCD (the dispatcher deals work-groups round-robin over the 8 XCDs), so

@@ -5,7 +5,8 @@
 //   2. eigendecomposition of C in FP64 (eigen_kernel: Householder
 //      tridiagonalisation, bisection on Sturm counts, inverse iteration for the
 //      clutter eigenvectors, back-transformation)
-//   3. removal I_f = I - (I V_c) V_c^H   (removal_kernel, FP64 accumulation)
+//   3. removal I_f = I - (I V_c) V_c^H   (removal_f64_kernel, FP64 MFMA;
+//      removal_bf16_kernel for the split-precision form)
 // Layout: a plane is stored frame-major, [F][n_pix] complex64, i.e. the
 // transpose of the Casorati matrix; the frame axis is the Gram's output axis
 // and the pixel axis its reduction axis.
@@ -754,58 +755,179 @@ __global__ void clear_status_kernel(int *status, int *bar, int *eflag, int plane
 }
 
 // ---------------------------------------------------------------- removal
-// The clutter eigenvectors copied to CM columns, zero past column c, so the
-// removal runs branch-free with compile-time strides (a zero column adds
-// exact zeros).
-__global__ void pad_subspace_kernel(const double2 *__restrict__ V, double2 *__restrict__ Vp, int F,
-                                    int c, int CM, int planes)
+// I_f = I - (I V_c) V_c^H on v_mfma_f64_16x16x4f64, both products transposed so
+// that the pixel is the MFMA's N index (a tile is 16 consecutive pixels):
+//   Y^T   = W1 X^T        row 2 i (re) and 2 i + 1 (im) of Y^T = (I V_c)[p][i];
+//                         K-step 2 q + r = frames 4 q .. 4 q + 3, their re (r = 0)
+//                         or im (r = 1) parts
+//   X_f^T = X^T - W2 Y^T  output tile tau = frames 8 tau .. 8 tau + 7: result
+//                         register r of lane l = frame 8 tau + 2 (l / 16) + r / 2,
+//                         re (r even) or im (r odd); K = the rows of Y^T, 4 a step
+// W1 and W2 are V_c's entries laid out as A operands (lane l: row l % 16, K index
+// l / 16), built per plane by removal_f64_tables_kernel, zero past 2c rows or F
+// frames.  FP32 inputs are exact in FP64, so only FP64 summation rounds.  The
+// first product's accumulators are the second's B operands as they stand:
+// register r of lane l in tile T holds row 16 T + 4 r + l / 16 of Y^T, which is
+// what lane l supplies for K-step 4 T + r.
+
+// One thread per (plane, table entry, lane).
+__global__ void removal_f64_tables_kernel(const double2 *__restrict__ V, double *__restrict__ tab,
+                                          int F, int c, Removal64Dims d, int planes)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= planes * F * CM) return;
-    const int col = i % CM, row = i / CM;              // row = plane * F + f
-    Vp[i] = col < c ? V[(size_t)row * c + col] : make_double2(0.0, 0.0);
+    const size_t n1 = (size_t)d.MT * d.KS1 * 64, n2 = (size_t)d.FT * d.KS2 * 64;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)planes * (n1 + n2)) return;
+    const int plane = (int)(idx / (n1 + n2));
+    const size_t e = idx % (n1 + n2);
+    const double2 *Vp = V + (size_t)plane * F * c;
+    const int lane = (int)(e % 64), m = lane & 15, k = lane >> 4;
+    double val = 0.0;
+    if (e < n1) {
+        // W1: tile T, step t; row 16 T + m of Y^T against (frame, part) of X^T
+        const int t = (int)((e / 64) % d.KS1), T = (int)(e / 64 / d.KS1);
+        const int row = 16 * T + m, i = row >> 1, yim = row & 1;
+        const int g = 4 * (t >> 1) + k, xim = t & 1;
+        if (i < c && g < F) {
+            const double2 v = Vp[(size_t)g * c + i];
+            // re y = xr vr - xi vi,  im y = xr vi + xi vr
+            val = yim ? (xim ? v.x : v.y) : (xim ? -v.y : v.x);
+        }
+    } else {
+        // W2: output tile tau, step s; output row m (frame, part) against row 4 s + k of Y^T
+        const size_t e2 = e - n1;
+        const int s = (int)((e2 / 64) % d.KS2), tau = (int)(e2 / 64 / d.KS2);
+        const int r = m >> 2, j = m & 3;
+        const int g = 8 * tau + 2 * j + (r >> 1), oim = r & 1;
+        const int yrow = 4 * s + k, i = yrow >> 1, yim = yrow & 1;
+        if (i < c && g < F) {
+            const double2 v = Vp[(size_t)g * c + i];
+            // y conj(v): re = yr vr + yi vi,  im = yi vr - yr vi
+            val = oim ? (yim ? v.x : -v.y) : (yim ? v.y : v.x);
+        }
+    }
+    tab[(size_t)plane * (n1 + n2) + e] = val;
 }
 
-// I_f = I - (I V_c) V_c^H per pixel time series, accumulated in FP64; one
-// thread per pixel, V (uniform across the wave) read through the scalar cache.
-template <int CM>
-__global__ __launch_bounds__(256) void removal_kernel(float2 *__restrict__ P,
-                                                      const double2 *__restrict__ V, int F,
-                                                      int npix, const int *__restrict__ eflag)
+// A wave owns kRemNT tiles of 16 pixels (the table operands are shared by them);
+// MT = tiles of 16 rows of Y^T.
+constexpr int kRemNT = 2;
+constexpr int kRemAhead = 4;       // frame groups of the plane in flight
+template <int MT>
+__global__ __launch_bounds__(256) void removal_f64_kernel(float2 *__restrict__ P,
+                                                          const double *__restrict__ tab, int F,
+                                                          int npix, Removal64Dims d,
+                                                          const int *__restrict__ eflag)
 {
     const int plane = blockIdx.y;
     if (eflag[plane]) return;      // non-finite covariance: the plane stays unfiltered
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    float2 *col = P + (size_t)plane * F * npix + p;
-    const double2 *Vp = V + (size_t)plane * F * CM;
-    double2 y[CM];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n16 = lane & 15, k4 = lane >> 4;
+    const int p0 = (blockIdx.x * 4 + wave) * 16 * kRemNT;
+    if (p0 >= npix) return;
+    float2 *X = P + (size_t)plane * F * npix;
+    const double *W1 = tab + (size_t)plane * (d.t1_plane + d.t2_plane);
+    const double *W2 = W1 + d.t1_plane;
+    int px[kRemNT];
+    bool pok[kRemNT];
 #pragma unroll
-    for (int i = 0; i < CM; ++i) y[i] = make_double2(0.0, 0.0);
-#pragma unroll 4
-    for (int g = 0; g < F; ++g) {
-        const float2 xf = col[(size_t)g * npix];
-        const double xr = xf.x, xi = xf.y;
-        const double2 *vg = Vp + (size_t)g * CM;
+    for (int nt = 0; nt < kRemNT; ++nt) {
+        px[nt] = p0 + 16 * nt + n16;
+        pok[nt] = px[nt] < npix;
+    }
+
+    // Y^T = W1 X^T: four frames per pair of K-steps.  The plane is read from
+    // HBM kRemAhead frame groups ahead (a ring of registers, the loop unrolled
+    // by its depth); the table operands (L2) one group ahead.
+    f64x4 y[MT][kRemNT];
 #pragma unroll
-        for (int i = 0; i < CM; ++i) {
-            const double2 v = vg[i];
-            y[i].x = fma(xr, v.x, fma(-xi, v.y, y[i].x));
-            y[i].y = fma(xr, v.y, fma(xi, v.x, y[i].y));
+    for (int T = 0; T < MT; ++T)
+#pragma unroll
+        for (int nt = 0; nt < kRemNT; ++nt) y[T][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int nq = d.KS1 / 2;
+    // past the last group the frame index is >= F: zeros, nothing read
+    auto load_x = [&](int q, float2 (&x)[kRemNT]) {
+        const int g = 4 * q + k4;
+#pragma unroll
+        for (int nt = 0; nt < kRemNT; ++nt)
+            x[nt] = (g < F && pok[nt]) ? X[(size_t)g * npix + px[nt]] : make_float2(0.f, 0.f);
+    };
+    auto load_w1 = [&](int q, double (&a)[MT][2]) {
+        const int qq = min(q, nq - 1);
+#pragma unroll
+        for (int T = 0; T < MT; ++T) {
+            a[T][0] = W1[((size_t)T * d.KS1 + 2 * qq) * 64 + lane];
+            a[T][1] = W1[((size_t)T * d.KS1 + 2 * qq + 1) * 64 + lane];
+        }
+    };
+    float2 xr[kRemAhead][kRemNT];
+    double aw[2][MT][2];
+#pragma unroll
+    for (int u = 0; u < kRemAhead; ++u) load_x(u, xr[u]);
+    load_w1(0, aw[0]);
+    for (int q0 = 0; q0 < nq; q0 += kRemAhead) {
+#pragma unroll
+        for (int u = 0; u < kRemAhead; ++u) {
+            const int q = q0 + u;
+            if (q < nq) {
+                load_w1(q + 1, aw[(u + 1) & 1]);
+#pragma unroll
+                for (int T = 0; T < MT; ++T)
+#pragma unroll
+                    for (int nt = 0; nt < kRemNT; ++nt) {
+                        y[T][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[u & 1][T][0], (double)xr[u][nt].x, y[T][nt], 0, 0, 0);
+                        y[T][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[u & 1][T][1], (double)xr[u][nt].y, y[T][nt], 0, 0, 0);
+                    }
+                load_x(q + kRemAhead, xr[u]);
+            }
         }
     }
-#pragma unroll 4
-    for (int f = 0; f < F; ++f) {
-        const float2 xf = col[(size_t)f * npix];
-        const double2 *vf = Vp + (size_t)f * CM;
-        double rr = 0.0, ri = 0.0;
+
+    // X_f^T = X^T - W2 Y^T, 8 frames per output tile; the inputs of the tile
+    // two ahead (read from HBM) are requested before this tile's products
+    auto load_out = [&](int tau, float2 (&x)[2][kRemNT]) {
+        const int g0 = 8 * tau + 2 * k4;
 #pragma unroll
-        for (int i = 0; i < CM; ++i) {
-            const double2 v = vf[i];                   // y * conj(v)
-            rr = fma(y[i].x, v.x, fma(y[i].y, v.y, rr));
-            ri = fma(y[i].y, v.x, fma(-y[i].x, v.y, ri));
+        for (int nt = 0; nt < kRemNT; ++nt) {
+            x[0][nt] = (g0 < F && pok[nt]) ? X[(size_t)g0 * npix + px[nt]] : make_float2(0.f, 0.f);
+            x[1][nt] = (g0 + 1 < F && pok[nt]) ? X[(size_t)(g0 + 1) * npix + px[nt]] : make_float2(0.f, 0.f);
         }
-        col[(size_t)f * npix] = make_float2((float)((double)xf.x - rr), (float)((double)xf.y - ri));
+    };
+    float2 xo[2][2][kRemNT];
+    load_out(0, xo[0]);
+    load_out(1, xo[1]);
+    for (int t0 = 0; t0 < d.FT; t0 += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int tau = t0 + u;
+            if (tau < d.FT) {
+                f64x4 o[kRemNT];
+#pragma unroll
+                for (int nt = 0; nt < kRemNT; ++nt) o[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+                const double *w2 = W2 + (size_t)tau * d.KS2 * 64 + lane;
+#pragma unroll
+                for (int T = 0; T < MT; ++T)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double a = w2[(size_t)(4 * T + r) * 64];
+#pragma unroll
+                        for (int nt = 0; nt < kRemNT; ++nt)
+                            o[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, y[T][nt][r], o[nt], 0, 0, 0);
+                    }
+                const int g0 = 8 * tau + 2 * k4;
+#pragma unroll
+                for (int nt = 0; nt < kRemNT; ++nt) {
+                    if (!pok[nt]) continue;
+                    const float2 x0 = xo[u][0][nt], x1 = xo[u][1][nt];
+                    if (g0 < F)
+                        X[(size_t)g0 * npix + px[nt]] = make_float2((float)((double)x0.x - o[nt][0]),
+                                                                    (float)((double)x0.y - o[nt][1]));
+                    if (g0 + 1 < F)
+                        X[(size_t)(g0 + 1) * npix + px[nt]] = make_float2((float)((double)x1.x - o[nt][2]),
+                                                                          (float)((double)x1.y - o[nt][3]));
+                }
+                load_out(tau + 2, xo[u]);
+            }
+        }
     }
 }
 
@@ -1080,20 +1202,18 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
             hipLaunchKernelGGL(removal_bf16_kernel<2>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (c > 0) {
-        const int CM = removal_cols(c);
-        double2 *Vp = (double2 *)(ws + w.vpad);
-        hipLaunchKernelGGL(pad_subspace_kernel, dim3(cdiv(planes * F * CM, 256)), dim3(256), 0, st,
-                           (const double2 *)(ws + w.evecs), Vp, F, c, CM, planes);
-        dim3 grid(cdiv(npix, 256), planes);
+        const Removal64Dims rd = removal64_dims(F, c);
+        double *tab = (double *)(ws + w.rtab64);
+        const size_t nthr = (size_t)planes * (rd.t1_plane + rd.t2_plane);
+        hipLaunchKernelGGL(removal_f64_tables_kernel, dim3((unsigned)cdiv<size_t>(nthr, 256)), dim3(256), 0,
+                           st, (const double2 *)(ws + w.evecs), tab, F, c, rd, planes);
+        dim3 grid(cdiv(npix, 4 * 16 * kRemNT), planes);
         const int *eflag = (const int *)(ws + w.eflag);
-        switch (CM) {
-            case 4: hipLaunchKernelGGL(removal_kernel<4>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            case 8: hipLaunchKernelGGL(removal_kernel<8>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            case 12: hipLaunchKernelGGL(removal_kernel<12>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            case 16: hipLaunchKernelGGL(removal_kernel<16>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            case 20: hipLaunchKernelGGL(removal_kernel<20>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            case 24: hipLaunchKernelGGL(removal_kernel<24>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
-            default: hipLaunchKernelGGL(removal_kernel<32>, grid, dim3(256), 0, st, proj, Vp, F, npix, eflag); break;
+        switch (rd.MT) {
+            case 1: hipLaunchKernelGGL(removal_f64_kernel<1>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag); break;
+            case 2: hipLaunchKernelGGL(removal_f64_kernel<2>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag); break;
+            case 3: hipLaunchKernelGGL(removal_f64_kernel<3>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag); break;
+            default: hipLaunchKernelGGL(removal_f64_kernel<4>, grid, dim3(256), 0, st, proj, tab, F, npix, rd, eflag); break;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -87,9 +87,9 @@ __device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
     const int e0 = min((int)threadIdx.x * R, npx), e1 = min(e0 + R, npx);
 
     // NCC threshold, 3x3 regional maximum (raster tie-break), then the intensity
-    // threshold (its global read only for the few regional maxima)
-    auto is_peak = [&](int e, float &I) {
-        const int rr = e / nu + 1, cc = e % nu + 1;          // position in the ncc array
+    // threshold (its global read only for the few regional maxima); (rr, cc) is
+    // the position in the ncc array
+    auto is_peak_at = [&](int rr, int cc, float &I) {
         const float n0 = ncc[rr * W_out + cc];
         if (!(n0 >= prm.tau)) return false;
         const float *up = ncc + (rr - 1) * W_out + cc;
@@ -102,13 +102,22 @@ __device__ void detect_band(const float *ncc, const float2 *__restrict__ src,
         I = sqrtf(x.x * x.x + x.y * x.y);
         return I >= thr_i;
     };
+    auto is_peak = [&](int e, float &I) { return is_peak_at(e / nu + 1, e % nu + 1, I); };
     unsigned long long mask = 0ull;                           // peaks among the run's first 64
     int cnt = 0;
-    for (int e = e0; e < e1; ++e) {
-        float I;
-        if (is_peak(e, I)) {
-            if (e - e0 < 64) mask |= 1ull << (e - e0);
-            ++cnt;
+    {
+        // the run's position advanced along the raster (one division per thread)
+        int rr = e0 / nu + 1, cc = e0 % nu + 1;
+        for (int e = e0; e < e1; ++e) {
+            float I;
+            if (is_peak_at(rr, cc, I)) {
+                if (e - e0 < 64) mask |= 1ull << (e - e0);
+                ++cnt;
+            }
+            if (++cc > nu) {
+                cc = 1;
+                ++rr;
+            }
         }
     }
     int incl = cnt;

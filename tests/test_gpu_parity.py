@@ -106,7 +106,10 @@ def _filter_input(F, nz, nu, seed):
     return st.reshape(2, 1, F, nz, nu)
 
 
-@pytest.mark.parametrize("F,nz,nu,c", [(20, 16, 20, 2), (70, 64, 70, 3), (130, 40, 37, 12)])
+# cutoffs 2, 3, 12 and 29 cover one to four 16-row tiles of the removal's 2c rows;
+# frames and pixels ragged against its 8-frame and 32-pixel tiles
+@pytest.mark.parametrize("F,nz,nu,c", [(20, 16, 20, 2), (70, 64, 70, 3), (130, 40, 37, 12),
+                                       (45, 24, 27, 29)])
 def test_filter_parity(torch, ulm, F, nz, nu, c):
     cfg = with_frames(cfg_tiny(), F)
     cfg = cfg.with_(svd_cutoff=c, grid=replace(cfg.grid, nz=nz, nu=nu, nv=nu))

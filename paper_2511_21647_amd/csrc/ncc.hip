@@ -323,27 +323,51 @@ __global__ __launch_bounds__(1024) void loc_scan_kernel(const int *__restrict__ 
                                                         int *__restrict__ off, int n,
                                                         int *__restrict__ count)
 {
-    __shared__ int s[1024];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < n; b0 += 1024) {
-        const int i = b0 + threadIdx.x;
-        const int v = i < n ? cnt[i] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            const int x = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-            __syncthreads();
-            s[threadIdx.x] += x;
-            __syncthreads();
+    // rounds of 4096 counts, 4 consecutive ones per thread: each wave scans its
+    // threads' sums with lane shuffles, the 16 wave totals meet in LDS (double-
+    // buffered by round parity: one barrier per round), and a running carry
+    // links the rounds; the next round's counts are loaded during this one
+    __shared__ int wtot[2][16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    auto load4 = [&](int b0, int (&v)[4]) {
+        const int i0 = b0 + 4 * t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = i0 + q < n ? cnt[i0 + q] : 0;
+    };
+    int cur[4], nxt[4];
+    load4(0, cur);
+    int carry = 0, par = 0;
+    for (int b0 = 0; b0 < n; b0 += 4096) {
+        load4(b0 + 4096, nxt);
+        const int sum = cur[0] + cur[1] + cur[2] + cur[3];
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
         }
-        if (i < n) off[i] = carry + s[threadIdx.x] - v;
+        if (lane == 63) wtot[par][wv] = incl;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += s[1023];
-        __syncthreads();
+        int base = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int x = wtot[par][q];
+            if (q < wv) base += x;
+            tot += x;
+        }
+        int run = carry + base + incl - sum;
+        const int i0 = b0 + 4 * t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (i0 + q < n) off[i0 + q] = run;
+            run += cur[q];
+        }
+        carry += tot;
+        par ^= 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
     }
-    if (threadIdx.x == 0) *count = carry;
+    if (t == 0) *count = carry;
 }
 
 __global__ __launch_bounds__(256) void loc_scatter_kernel(

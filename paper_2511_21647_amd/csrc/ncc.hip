@@ -323,10 +323,10 @@ __global__ __launch_bounds__(1024) void loc_scan_kernel(const int *__restrict__ 
                                                         int *__restrict__ off, int n,
                                                         int *__restrict__ count)
 {
-    // rounds of 4096 counts, 4 consecutive ones per thread: each wave scans its
+    // passes of 4096 counts, 4 consecutive ones per thread: each wave scans its
     // threads' sums with lane shuffles, the 16 wave totals meet in LDS (double-
-    // buffered by round parity: one barrier per round), and a running carry
-    // links the rounds; the next round's counts are loaded during this one
+    // buffered by pass parity: one barrier per pass), and a running carry links
+    // the passes; the next pass's counts are loaded during this one
     __shared__ int wtot[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     auto load4 = [&](int b0, int (&v)[4]) {

@@ -355,34 +355,40 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(const float2 *__res
     }
 }
 
-// Sum the chunk partials in FP64 and write the full Hermitian C[plane][F][F].
-__global__ void gram_reduce_kernel(const double2 *__restrict__ part, double2 *__restrict__ C,
-                                   int F, int pairs, int chunks, int nblk, int planes)
+// Sum of the per-chunk partials of C.  One work-group per (plane, block pair
+// I <= J, 4 rows of the 64 x 64 block): thread (row, column) adds its element
+// over the pixel chunks in chunk order, so a row of 64 partials is one
+// contiguous read, and writes it to C with its mirror: the conjugate into
+// block (J, I), and in a diagonal block the upper-right quadrant's conjugate
+// into the lower-left one (whose partials the Gram kernels do not form).
+constexpr int kReduceRows = 4;
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2 *__restrict__ part,
+                                                          double2 *__restrict__ C, int F, int pairs,
+                                                          int chunks, int nblk)
 {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)planes * F * F) return;
-    const int plane = (int)(idx / ((size_t)F * F));
-    const int f1 = (int)((idx / F) % F), f2 = (int)(idx % F);
-    int a = f1, b = f2;
-    // blocks below the diagonal, and the lower-left quadrant of a diagonal
-    // block, are read from their mirror image
-    const bool swap = (f1 / kGramBlock) > (f2 / kGramBlock) ||
-                      ((f1 / kGramBlock) == (f2 / kGramBlock) && (f1 % kGramBlock) >= kGramBlock / 2 &&
-                       (f2 % kGramBlock) < kGramBlock / 2);
-    if (swap) { a = f2; b = f1; }
-    const int I = a / kGramBlock, J = b / kGramBlock;
-    int pair = 0;
-    for (int i = 0; i < I; ++i) pair += nblk - i;
-    pair += J - I;
+    constexpr int kStrips = kGramBlock / kReduceRows;
+    const int strip = blockIdx.x % kStrips;
+    const int pair = (blockIdx.x / kStrips) % pairs;
+    const int plane = blockIdx.x / (kStrips * pairs);
+    int I, J;
+    pair_of(pair, nblk, I, J);
+    const int r = strip * kReduceRows + (threadIdx.x >> 6), c = threadIdx.x & 63;
+    const bool diag = I == J;
+    if (diag && r >= kGramBlock / 2 && c < kGramBlock / 2) return;
+    const int f1 = I * kGramBlock + r, f2 = J * kGramBlock + c;
+    if (f1 >= F || f2 >= F) return;
     const double2 *src = part + (size_t)(plane * pairs + pair) * chunks * kGramBlock * kGramBlock +
-                         (a % kGramBlock) * kGramBlock + (b % kGramBlock);
+                         r * kGramBlock + c;
     double re = 0.0, im = 0.0;
-    for (int c = 0; c < chunks; ++c) {
-        const double2 v = src[(size_t)c * kGramBlock * kGramBlock];
+#pragma unroll 8
+    for (int ch = 0; ch < chunks; ++ch) {
+        const double2 v = src[(size_t)ch * kGramBlock * kGramBlock];
         re += v.x;
         im += v.y;
     }
-    C[idx] = make_double2(re, swap ? -im : im);
+    double2 *Cp = C + (size_t)plane * F * F;
+    Cp[(size_t)f1 * F + f2] = make_double2(re, im);
+    if (!diag || (r < kGramBlock / 2 && c >= kGramBlock / 2)) Cp[(size_t)f2 * F + f1] = make_double2(re, -im);
 }
 
 // ---------------------------------------------------------------- eigensolver
@@ -1149,9 +1155,8 @@ hipError_t launch_filter(const ulm_ctx *ctx, float2 *proj, double *eigvals_out, 
                            w.gram_pairs, w.gram_chunks, nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t nC = (size_t)planes * F * F;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)cdiv<size_t>(nC, 256)), dim3(256), 0, st,
-                       part, C, F, w.gram_pairs, w.gram_chunks, nblk, planes);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(planes * w.gram_pairs * (kGramBlock / kReduceRows)),
+                       dim3(256), 0, st, part, C, F, w.gram_pairs, w.gram_chunks, nblk);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     double *evals = (double *)(ws + w.evals);

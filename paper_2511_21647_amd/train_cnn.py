@@ -60,21 +60,22 @@ def init_flat(seed: int) -> np.ndarray:
 class Simulator:
     """Paper-scale ensemble -> filtered planes, CNN images and labels on the GPU."""
 
-    def __init__(self, precision=None):
+    def __init__(self, precision=None, blocks=1):
         import torch
         import paper_2511_21647_amd as ulm
-        from synth import cfg_cnn
+        from synth import cfg_cnn, with_blocks
         self.torch, self.ulm = torch, ulm
-        self.cfg = cfg_cnn(2000)
+        self.blocks = blocks
+        self.cfg = with_blocks(cfg_cnn(2000), blocks)
         prec = ulm.ULM_PREC_BF16X3 if precision is None else precision
         self.ctx = ulm.Context(self.cfg, precision=prec)
         self.iq = torch.empty(self.ctx.iq_shape, dtype=torch.complex64, device="cuda")
         self.proj = torch.empty(self.ctx.proj_shape, dtype=torch.complex64, device="cuda")
 
     def ensemble(self, e: int):
-        from synth import cfg_cnn, make_medium, plane_positions
+        from synth import cfg_cnn, make_medium, plane_positions, with_blocks
         torch, ulm = self.torch, self.ulm
-        cfg = cfg_cnn(n_mb_for(e))
+        cfg = with_blocks(cfg_cnn(n_mb_for(e)), self.blocks)
         med = make_medium(cfg, e)
         pos = torch.from_numpy(med.pos).cuda()
         amp = torch.from_numpy(med.amp).cuda()
@@ -244,17 +245,24 @@ def _score_ensemble(e, n_mb, ncc, truth, cnn_by_thr):
     ncc_t = [x[ncc_true[counts[k]:counts[k + 1]]] for k, x in enumerate(ncc)]
     r = {"ensemble": e, "n_mb": n_mb, "ncc_vs_truth": score(ncc, truth), "cnn": {}}
     for thr, cnn in cnn_by_thr.items():
+        if cnn is None:
+            r["cnn"][thr] = {"overflow": True}
+            continue
         r["cnn"][thr] = {"vs_truth": score(cnn, truth), "vs_ncc": score(cnn, ncc),
                          "vs_ncc_true": score(cnn, ncc_t)}
     return r
 
 
-def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log, workers=4):
+def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=log, workers=4,
+             blocks=1):
     """NCC and CNN on held-out ensembles: each against the truth, and the CNN
     against NCC as the reference (all NCC detections, and NCC's true detections),
-    for every CNN decode threshold given.  The matching runs in `workers` CPU
-    processes, forked before the GPU is touched, while the GPU localises the
-    next ensembles."""
+    for every CNN decode threshold given.  With `blocks` > 1 the planes are the
+    slab projections of the sub-block form (Section II-A4): each image sums
+    `ceil(Nv / blocks)` slices, so it holds that fraction of the MBs, and the
+    truth of a slab image is the MBs whose v lies in its slab.  The matching runs
+    in `workers` CPU processes, forked before the GPU is touched, while the GPU
+    localises the next ensembles."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     pool = ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) if workers > 0 else None
@@ -262,12 +270,12 @@ def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=
         list(pool.map(abs, range(workers)))      # start the workers now
     import torch
     import paper_2511_21647_amd as ulm
-    sim = Simulator()
+    sim = Simulator(blocks=blocks)
     cfg = sim.cfg
     F = cfg.seq.n_frames
-    n_img = 2 * F
+    n_img = 2 * blocks * F
     params = torch.from_numpy(np.asarray(weights, np.float32)).cuda()
-    cap = 4_000_000
+    cap = 4_000_000 if blocks == 1 else 1 << 25
     locs = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
     cws = ulm.Workspace(ulm.ulm_cnn_localize_workspace_size(sim.ctx, 64), "cuda")
@@ -283,7 +291,16 @@ def evaluate(weights, ensembles, thresholds=(0.5,), seed0=HELDOUT_SEED0, log_fn=
         for thr in thresholds:
             ulm.ulm_cnn_localize(sim.ctx, params, sim.proj, cap, thr, 64, ulm.ULM_CNN_BF16,
                                  locs, count, ws=cws)
-            ulm.ulm_check_status(sim.ctx, count, cap)
+            try:
+                ulm.ulm_check_status(sim.ctx, count, cap)
+            except ulm.ULMError as err:
+                # more peaks than an image row's staging slot or the capacity: the
+                # threshold is recorded as overflowing instead of scored
+                if err.code != ulm.ULM_ERR_OVERFLOW:
+                    raise
+                by_thr[str(thr)] = None
+                log_fn(f"ensemble {e}: CNN threshold {thr} overflows ({int(count.item())} peaks)")
+                continue
             by_thr[str(thr)] = per_image(ulm.locs_to_numpy(locs, count), n_img, F)
         args = (e, n_mb, ncc, truth, by_thr)
         jobs.append(pool.submit(_score_ensemble, *args) if pool else args)
@@ -333,11 +350,15 @@ def main():
     ap.add_argument("--thresholds", default="0.5",
                     help="comma-separated CNN decode thresholds to evaluate")
     ap.add_argument("--workers", type=int, default=4, help="CPU processes for the matching")
+    ap.add_argument("--blocks", type=int, default=1,
+                    help="slabs per orientation for --evaluate (35: the P = 8 sub-block planes)")
     args = ap.parse_args()
     if args.evaluate:
         thr = tuple(float(x) for x in args.thresholds.split(","))
-        res = evaluate(np.load(args.evaluate), args.ensembles, thr, workers=args.workers)
-        with open(os.path.splitext(args.evaluate)[0] + "_eval.json", "w") as fh:
+        res = evaluate(np.load(args.evaluate), args.ensembles, thr, workers=args.workers,
+                       blocks=args.blocks)
+        suffix = "_eval.json" if args.blocks == 1 else "_eval_slabs.json"
+        with open(os.path.splitext(args.evaluate)[0] + suffix, "w") as fh:
             json.dump(res, fh, indent=1)
     else:
         train(args)

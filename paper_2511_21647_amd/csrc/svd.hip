@@ -99,8 +99,11 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const float2 *__restrict_
         }
         __syncthreads();
         if (p0 + kGramStage < px1) fetch(p0 + kGramStage);
-#pragma unroll 4
-        for (int step = 0; step < (mirror ? 0 : kGramStage / 2); ++step) {
+        // the mirror wave of a diagonal block forms nothing; the others' 16
+        // steps are unrolled whole (a static trip count)
+        if (!mirror)
+#pragma unroll
+        for (int step = 0; step < kGramStage / 2; ++step) {
             const int pxl = step * 2 + (kk >> 1);
             const bool im = kk & 1;
             double a[2], br[2], bi[2];
